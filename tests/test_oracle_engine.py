@@ -1,0 +1,210 @@
+"""Pins of the oracle's agent orders, step loop and statistics.
+
+Whole trajectories have no printed values in the paper (its Table II uses another generator
+and unstated agent parameters), so they are pinned by properties that any correct engine has:
+step-split invariance, independence of markets, invariance under the order in which agents
+are aggregated, and the clearing invariants at every step.  The agent rules (section III-C)
+are pinned by their closed-form distributions and by hand cases; the statistics by a hand
+case with known values.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import stats
+
+
+def test_noise_orders_distribution(orc):
+    """Offsets are uniform on {-K..K}, quantities on {1..Q}, sides a fair coin."""
+    L, A, K, Q = 256, 4096, 16, 100
+    d = orc.market(L, A, K, Q)
+    sides, offs, qtys = [], [], []
+    for s in range(8):
+        side, tick, qty = orc.orders(d, 5, 1, s, 128, 128)
+        sides.append(side)
+        offs.append(tick.astype(int) - 128)
+        qtys.append(qty)
+    side, off, qty = map(np.concatenate, (sides, offs, qtys))
+    assert off.min() == -K and off.max() == K
+    assert qty.min() == 1 and qty.max() == Q
+    assert set(np.unique(side)) == {0, 1}
+    for x, lo, n in ((off, -K, 2 * K + 1), (qty, 1, Q), (side, 0, 2)):
+        obs = np.bincount(x - lo, minlength=n)
+        starts = np.array([-(-(v << 32) // n) for v in range(n + 1)], dtype=np.float64)
+        starts[-1] = 2.0**32
+        exp = np.diff(starts) / 2.0**32 * len(x)
+        chi2 = ((obs - exp) ** 2 / exp).sum()
+        assert 1.0 - stats.chi2.cdf(chi2, n - 1) > 1e-4
+    # side and offset come from different words: independent
+    tab = np.zeros((2, 2 * K + 1))
+    np.add.at(tab, (side, off + K), 1)
+    assert stats.chi2_contingency(tab)[1] > 1e-4
+
+
+def test_noise_orders_clamped_to_grid(orc):
+    L, A, K, Q = 64, 2048, 8, 10
+    d = orc.market(L, A, K, Q)
+    for last in (0, 3, 60, 63):
+        side, tick, qty = orc.orders(d, 0, 0, 11, last, last)
+        assert tick.min() >= 0 and tick.max() <= L - 1
+        lo, hi = max(0, last - K), min(L - 1, last + K)
+        assert tick.min() == lo and tick.max() == hi
+        # every offset that falls off the grid lands on the edge tick
+        if last - K < 0:
+            frac = np.mean(tick == 0)
+            assert abs(frac - (K - last + 1) / (2 * K + 1)) < 0.05
+
+
+def test_momentum_and_maker_rules(orc):
+    L, A, K, Q, h = 64, 300, 8, 10, 3
+    d = orc.market(L, A, K, Q, n_noise=100, n_mom=100, h=h)
+    mom = slice(100, 200)
+    mk = np.arange(200, 300)
+    for s in (4, 5):
+        # price went up: every momentum agent buys one tick above the reference
+        side, tick, qty = orc.orders(d, 2, 9, s, 30, 29)
+        assert np.all(side[mom] == orc.BUY) and np.all(tick[mom] == 31)
+        # price went down: they sell one tick below
+        side, tick, qty = orc.orders(d, 2, 9, s, 30, 31)
+        assert np.all(side[mom] == orc.SELL) and np.all(tick[mom] == 29)
+        # unchanged: a fair coin, still one tick away in the side's direction
+        side, tick, qty = orc.orders(d, 2, 9, s, 30, 30)
+        buys = side[mom] == orc.BUY
+        assert 0 < buys.sum() < 100
+        assert np.all(tick[mom][buys] == 31) and np.all(tick[mom][~buys] == 29)
+        # makers alternate with the parity of agent index + step, h ticks from the reference
+        want_buy = ((mk + s) % 2) == 0
+        assert np.all((side[200:] == orc.BUY) == want_buy)
+        assert np.all(tick[200:][want_buy] == 30 - h)
+        assert np.all(tick[200:][~want_buy] == 30 + h)
+        assert qty.min() >= 1 and qty.max() <= Q
+    # clamping at the grid edges
+    side, tick, qty = orc.orders(d, 2, 9, 4, 0, 1)
+    assert np.all(tick[mom] == 0)
+    side, tick, qty = orc.orders(d, 2, 9, 4, 63, 62)
+    assert np.all(tick[mom] == 63)
+    side, tick, qty = orc.orders(d, 2, 9, 4, 1, 1)
+    assert np.all(tick[200:][side[200:] == orc.BUY] == 0)
+
+
+def test_initial_state(orc):
+    for L in (1, 5, 64, 1024):
+        st = orc.initial_state(orc.market(L, 8, 1, 1))
+        assert st["last"][0] == L // 2 and st["prev"][0] == L // 2
+        assert st["steps_done"][0] == 0 and st["n_trade"][0] == 0
+
+
+def test_stats_hand_case(orc):
+    """Three finished steps on L = 4 with hand-computed statistics."""
+    L = 4
+    lnp = np.log(np.array([4.0, 5.0, 6.0, 7.0]))
+    st = orc.initial_state(orc.market(L, 1, 1, 1))  # last = prev = 2
+    # step 1: traded 5 at tick 2; residual bid at 0, ask at 3 -> spread 3; price unchanged
+    orc.update_stats([1, 0, 0, 0], [0, 0, 0, 3], 2, 5, lnp, st)
+    # step 2: nothing traded; residual only a bid -> no spread
+    orc.update_stats([2, 0, 0, 0], [0, 0, 0, 0], 0, 0, lnp, st)
+    # step 3: traded 4 at tick 3; bid at 1, ask at 3 -> spread 2; return ln 7 - ln 6
+    orc.update_stats([0, 1, 0, 0], [0, 0, 0, 1], 3, 4, lnp, st)
+    s = st[0]
+    assert s["last"] == 3 and s["prev"] == 2 and s["steps_done"] == 3
+    assert s["n_trade"] == 2 and s["sum_vol"] == 9 and s["sum_px"] == 5
+    assert s["sum_spread"] == 5 and s["n_spread"] == 2
+    r = math.log(7.0) - math.log(6.0)
+    assert s["sum_r"] == r and s["sum_r2"] == r * r
+
+
+def _python_step(orc, d, m, seed, st, bid, ask):
+    """One step assembled from the oracle's pieces, checking every clearing invariant."""
+    L = int(d["L"][0])
+    side, tick, qty = orc.orders(d, m, seed, int(st["steps_done"][0]), int(st["last"][0]),
+                                 int(st["prev"][0]))
+    b = bid.astype(np.int64).copy()
+    a = ask.astype(np.int64).copy()
+    np.add.at(b, tick[side == orc.BUY], qty[side == orc.BUY])
+    np.add.at(a, tick[side == orc.SELL], qty[side == orc.SELL])
+    p, v, nb, na = orc.clear(b, a)
+    fb, fs = b - nb.astype(np.int64), a - na.astype(np.int64)
+    assert fb.sum() == v and fs.sum() == v and fb.min() >= 0 and fs.min() >= 0
+    D = np.cumsum(b[::-1])[::-1]
+    S = np.cumsum(a)
+    assert v == np.minimum(D, S).max()
+    if v:
+        assert v == min(D[p], S[p]) and np.all(np.minimum(D, S)[:p] < v)
+    hb, la = np.nonzero(nb)[0], np.nonzero(na)[0]
+    if len(hb) and len(la):
+        assert hb.max() < la.min()
+    orc.update_stats(nb, na, p, v, orc.log_prices(L), st)
+    return nb, na
+
+
+@pytest.mark.parametrize("cfg", [(64, 128, 8, 10, 128, 0, 2), (32, 40, 4, 7, 20, 10, 1),
+                                 (8, 33, 3, 5, 11, 11, 2)])
+def test_trajectory_invariants_and_assembly(orc, cfg):
+    L, A, K, Q, nn, nm, h = cfg
+    d = orc.market(L, A, K, Q, n_noise=nn, n_mom=nm, h=h)
+    m, seed, S = 3, 77, 40
+    st = orc.initial_state(d)
+    bid = np.zeros(L, np.uint32)
+    ask = np.zeros(L, np.uint32)
+    for _ in range(S):
+        bid, ask = _python_step(orc, d, m, seed, st, bid, ask)
+    st2, bk2 = orc.market_run(d, m, seed, S)
+    assert st2.tobytes() == st.tobytes()
+    assert bk2.tolist() == bid.tolist() + ask.tolist()
+
+
+def test_step_split_invariance(orc):
+    d = orc.market(64, 128, 8, 10)
+    st_a, bk_a = orc.market_run(d, 1, 0, 100)
+    st_b, bk_b = orc.market_run(d, 1, 0, 37)
+    st_b, bk_b = orc.market_run(d, 1, 0, 63, state=st_b, book=bk_b)
+    assert st_a.tobytes() == st_b.tobytes()
+    assert np.array_equal(bk_a, bk_b)
+
+
+def test_market_independence(orc):
+    descs = np.concatenate([orc.market(64, 128, 8, 10) for _ in range(4)])
+    st, bk = orc.run(descs, 0, 50)
+    for m in range(4):
+        s1, b1 = orc.market_run(descs[m:m + 1], m, 0, 50)
+        assert s1.tobytes() == st[m:m + 1].tobytes()
+        assert np.array_equal(b1, bk[m * 128:(m + 1) * 128])
+    # a sampled sub-ensemble with explicit market ids reproduces the same slices
+    st2, bk2 = orc.run(descs[[3, 1]], 0, 50, ids=[3, 1])
+    assert st2[0].tobytes() == st[3].tobytes() and st2[1].tobytes() == st[1].tobytes()
+
+
+def test_agent_order_invariance(orc):
+    d = orc.market(64, 100, 8, 10, n_noise=60, n_mom=20, h=2)
+    rng = np.random.default_rng(3)
+    s1, b1 = orc.market_run(d, 2, 5, 60)
+    s2, b2 = orc.market_run(d, 2, 5, 60, agent_order=rng.permutation(100))
+    assert s1.tobytes() == s2.tobytes() and np.array_equal(b1, b2)
+
+
+def test_seed_and_market_change_the_stream(orc):
+    d = orc.market(64, 128, 8, 10)
+    _, b0 = orc.market_run(d, 0, 0, 20)
+    _, b1 = orc.market_run(d, 1, 0, 20)
+    _, b2 = orc.market_run(d, 0, 1, 20)
+    _, b3 = orc.market_run(d, 0, 1 << 32, 20)
+    assert not np.array_equal(b0, b1) and not np.array_equal(b0, b2)
+    assert not np.array_equal(b2, b3)
+
+
+def test_overflow_guard(orc):
+    d = orc.market(8, 1 << 16, 1, 1 << 15)  # 2^31 per step
+    orc.market_run(d, 0, 0, 1)
+    with pytest.raises(ValueError):
+        orc.market_run(d, 0, 0, 2)
+
+
+def test_paper_scale_sanity(orc):
+    """At the paper's shape (L = 128, A = 256) the price stays near the centre and volume per
+    step is of the order of the quantity posted near the reference (section IV, Table II
+    reports a mean clearing tick of 63.94 for its own agent mix)."""
+    d = np.concatenate([orc.market(128, 256, 8, 10) for _ in range(16)])
+    st, _ = orc.run(d, 0, 200)
+    mean_px = st["sum_px"].sum() / st["n_trade"].sum()
+    assert 44 < mean_px < 84
+    assert st["n_trade"].min() > 150
