@@ -1,0 +1,187 @@
+/*
+ * cae.h -- C ABI of libcae: a call-auction ensemble engine for AMD Instinct MI355X (gfx950).
+ *
+ * The engine steps many independent limit-order books through repeated uniform-price call
+ * auctions (KineticSim paper, section II-A, Eq. 1 and Eq. 2): every agent posts an order,
+ * the orders are aggregated per tick, cumulative demand D(p) = sum_{q>=p} BUY[q] and supply
+ * S(p) = sum_{q<=p} SELL[q] are formed, the market clears at the lowest tick maximising
+ * min(D, S), fills go by price priority and the residual book carries to the next step.
+ * All S steps of a call run in one persistent kernel launch with the books resident in LDS
+ * (section III, Algorithm 1); HBM is touched only when a call starts and ends.
+ *
+ * Conventions for every function below:
+ *   - the return value is CAE_OK (0) or a negative CAE_E* code; cae_last_error() then
+ *     holds a message for the calling thread;
+ *   - "device" pointers are HIP device memory owned by the caller (for example the data
+ *     pointers of torch tensors); the library never allocates or frees device memory;
+ *   - "host" pointers are ordinary host memory owned by the caller;
+ *   - a stream is a hipStream_t passed as void* (NULL = the default stream); work is
+ *     ordered on it and the calls marked "asynchronous" return before it completes;
+ *   - an ensemble handle must not be used from two host threads or two streams at once.
+ *
+ * Orders (section III-C, readings of this library):
+ *   agent a of market m at absolute step s draws w = Philox4x32-10(counter (s, a, m, 0),
+ *   key (seed mod 2^32, seed / 2^32)) (Salmon et al., SC'11; the paper's counter-based
+ *   generator of section III-G).  With ref = the last clearing tick:
+ *     NOISE    (a < n_noise):          side BUY iff w0 < 2^31; tick = ref + floor(w1*(2K+1)/2^32) - K
+ *     MOMENTUM (a < n_noise + n_mom):  side = sign(last - prev) (BUY up, SELL down, w0 rule if 0);
+ *                                      tick = ref + 1 for BUY, ref - 1 for SELL
+ *     MAKER    (the rest):             BUY iff (a + s) is even; tick = ref - h (BUY) or ref + h (SELL)
+ *   every tick is clamped to [0, L-1]; quantity = 1 + floor(w2 * Q / 2^32).
+ * Clearing: the combined book (resting + new) clears at p*, the lowest tick of maximal
+ * V(p) = min(D(p), S(p)); bids fill from the highest tick down and asks from the lowest tick
+ * up until V* shares each.  If V* = 0 nothing trades and the price is unchanged.
+ * Statistics per step: prev <- last; if V* > 0 then last <- p*, n_trade += 1,
+ * sum_vol += V*, sum_px += p*; if the residual book has both a best bid bb and a best ask ba,
+ * sum_spread += ba - bb and n_spread += 1; r = ln(L + last) - ln(L + prev), sum_r += r,
+ * sum_r2 += r * r (double, no fused multiply-add).  The opening book is empty and
+ * last = prev = floor(L / 2).
+ */
+#ifndef CAE_H
+#define CAE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Return codes. */
+#define CAE_OK 0
+#define CAE_EINVAL (-1)    /* bad argument or descriptor; nothing was launched             */
+#define CAE_EOVERFLOW (-2) /* the call could overflow a 32-bit book; nothing was launched   */
+#define CAE_ENOSPACE (-3)  /* a caller buffer is smaller than required                      */
+#define CAE_EHIP (-4)      /* the HIP runtime reported an error (message has its text)      */
+#define CAE_ESTATE (-5)    /* the handle is not in a state that allows the call             */
+
+/* One market (32 bytes).  Constraints checked by cae_sizes and cae_create:
+ *   1 <= L <= 1024, A >= 1, K <= 2^30, Q >= 1, A * Q < 2^32, n_noise + n_mom <= A,
+ *   maker_half_spread < L, flags == 0. */
+typedef struct cae_market {
+    uint32_t L;                 /* ticks on the price grid                                */
+    uint32_t A;                 /* agents                                                 */
+    uint32_t K;                 /* noise offsets are uniform on {-K..K}                   */
+    uint32_t Q;                 /* quantities are uniform on {1..Q}                       */
+    uint32_t n_noise;           /* agents [0, n_noise) are NOISE                          */
+    uint32_t n_mom;             /* agents [n_noise, n_noise + n_mom) MOMENTUM; rest MAKER */
+    uint32_t maker_half_spread; /* h, in ticks                                            */
+    uint32_t flags;             /* must be 0                                              */
+} cae_market;
+
+/* Per-market state and statistics (72 bytes, this exact layout in device memory). */
+typedef struct cae_state {
+    uint32_t last;       /* last clearing tick                                 */
+    uint32_t prev;       /* reference before the last step                     */
+    uint64_t steps_done; /* absolute step counter (the generator's counter)     */
+    uint64_t n_trade;
+    uint64_t sum_vol;
+    uint64_t sum_px;
+    uint64_t sum_spread;
+    uint64_t n_spread;
+    double sum_r;
+    double sum_r2;
+} cae_state;
+
+/* Device memory an ensemble needs (from cae_sizes). */
+typedef struct cae_sizes_t {
+    uint64_t book_words;      /* uint32 words of the packed books: sum over markets of 2*L */
+    uint64_t book_bytes;      /* 4 * book_words                                             */
+    uint64_t state_bytes;     /* M * sizeof(cae_state)                                      */
+    uint64_t workspace_bytes; /* library-private workspace (descriptors, schedule, tables)  */
+} cae_sizes_t;
+
+/* Caller-owned device buffers, each at least the size cae_sizes reports, 256-byte aligned.
+ * book:  market m occupies words [2*o_m, 2*o_m + 2*L_m), o_m = sum_{j<m} L_j; bid[0..L)
+ *        then ask[0..L), uint32 per tick (structure of arrays per market).
+ * state: M cae_state records in market order.
+ * workspace: opaque; must not be modified while the ensemble exists. */
+typedef struct cae_buffers {
+    uint32_t *book;
+    cae_state *state;
+    void *workspace;
+} cae_buffers;
+
+/* Schedule of the persistent launch.  Zero fields mean "choose automatically"; an
+ * autotuner result can be passed back in.  waves_per_market[c] applies to size class c
+ * (class = index of the smallest of 64,128,256,512,1024 that is >= L, times 8, plus the
+ * A bucket floor(log2(A)) clamped to 6..13 minus 6): 40 classes. */
+#define CAE_NUM_CLASSES 40
+typedef struct cae_tuning {
+    uint32_t waves_per_group;                   /* waves per workgroup (1..16)           */
+    uint32_t groups_per_cu;                     /* resident workgroups per CU to launch   */
+    uint32_t max_lds_bytes;                     /* LDS budget per workgroup               */
+    uint32_t flags;                             /* bit 0: keep descriptor order (no LPT)  */
+    uint8_t waves_per_market[CAE_NUM_CLASSES];  /* 1,2,4,8,16 per size class; 0 = auto    */
+} cae_tuning;
+
+typedef struct cae_ensemble cae_ensemble;
+
+/* Text for a return code.  Never NULL. */
+const char *cae_strerror(int code);
+
+/* Message of the last failing call on this host thread ("" if none).  Never NULL. */
+const char *cae_last_error(void);
+
+/* Library and device information: number of compute units of the current device and the
+ * library version.  Either pointer may be NULL. */
+int cae_device_info(uint32_t *num_cu, uint32_t *version);
+
+/* Sizes of the device buffers for M markets described by host array desc[M].  Pure host
+ * computation.  CAE_EINVAL on a bad descriptor (the message names the market). */
+int cae_sizes(const cae_market *desc, uint32_t M, cae_sizes_t *out);
+
+/* Create an ensemble of M markets (Algorithm 1, "REQUIRE": M markets with their A agents
+ * and L ticks; section III-B: books start empty at the opening price).  Copies the
+ * descriptors and schedule into dev->workspace, zeroes dev->book and writes the opening
+ * state to dev->state, ordered on `stream`; returns after those copies completed.
+ * tuning may be NULL (automatic schedule).  *out receives a host handle that owns only
+ * host memory.  Errors: CAE_EINVAL (descriptor, M == 0, NULL pointer), CAE_EHIP. */
+int cae_create(const cae_market *desc, uint32_t M, uint64_t seed, const cae_buffers *dev,
+               void *stream, const cae_tuning *tuning, cae_ensemble **out);
+
+/* Advance every market by S steps in one persistent launch on the ensemble's stream
+ * (Algorithm 1: the S-step loop runs on the device; section III-E phases 2-5 each step).
+ * Asynchronous.  Fails with CAE_EOVERFLOW, launching nothing, if for some market
+ * (steps_done + S) * A * Q >= 2^32 (a 32-bit book could then overflow).  S == 0 is a
+ * no-op.  Errors: CAE_EINVAL, CAE_EOVERFLOW, CAE_EHIP. */
+int cae_step(cae_ensemble *e, uint32_t S);
+
+/* Copy the packed books (layout of cae_buffers.book) to host_book[n_words] after the
+ * stream's pending work; returns when the copy is complete.  CAE_ENOSPACE if n_words is
+ * smaller than book_words. */
+int cae_read_books(cae_ensemble *e, uint32_t *host_book, uint64_t n_words);
+
+/* Copy the M states to host_state[M]; synchronous like cae_read_books. */
+int cae_read_state(cae_ensemble *e, cae_state *host_state, uint32_t M);
+
+/* Replace the device books and states with host copies (checkpoint resume).  host_book
+ * must hold book_words words in the packed layout.  CAE_EINVAL if M or n_words do not
+ * match the ensemble or a state is inconsistent with its market (last or prev >= L). */
+int cae_write_state(cae_ensemble *e, const cae_state *host_state, uint32_t M,
+                    const uint32_t *host_book, uint64_t n_words);
+
+/* The schedule in use (as chosen at create).  */
+int cae_get_tuning(const cae_ensemble *e, cae_tuning *out);
+
+/* Duration in milliseconds of the last cae_step launch, from HIP events recorded on the
+ * ensemble's stream around the kernel; waits for that launch to finish. */
+int cae_last_step_ms(cae_ensemble *e, float *ms);
+
+/* Release the host handle.  Device buffers stay owned by the caller. */
+int cae_destroy(cae_ensemble *e);
+
+/* One clearing pass over M books of L ticks each (Eq. 1, Eq. 2 and price-priority fill;
+ * the worked example of section IV-C is one such book).  dev_book holds M books in the
+ * packed layout (bid[L] then ask[L] per book) and is updated in place to the residual
+ * books; dev_pstar[M] receives the lowest tick of maximal volume (0 when nothing can trade)
+ * and dev_vstar[M] the executed volume.  Every per-book total must be below 2^32.
+ * Asynchronous on `stream`.  Errors: CAE_EINVAL (L outside 1..1024, NULL), CAE_EHIP. */
+int cae_clear(uint32_t L, uint32_t M, uint32_t *dev_book, uint32_t *dev_pstar,
+              uint32_t *dev_vstar, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CAE_H */

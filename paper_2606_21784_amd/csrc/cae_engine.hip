@@ -1,0 +1,1019 @@
+// cae_engine.hip -- persistent call-auction ensemble engine for gfx950 (MI355X) and its C ABI.
+//
+// Method: KineticSim paper, section II-A (Eq. 1, Eq. 2: cumulative demand/supply, clearing price
+// of maximal executable volume), section III-B..E (books resident in on-chip memory for all S
+// steps of a launch, orders aggregated with on-chip atomics, cooperative clearing, residual book
+// carried across steps), Algorithm 1 (the persistent per-market step loop).
+//
+// gfx950 design (what differs from the paper's CUDA design, and why):
+//   * A market is owned by a group of `wpm` wave64s (1..16).  All of them generate orders
+//     (agents strided over the group's lanes) and add them to the book in LDS with ds_add_u32.
+//     ONE wave then clears the whole book: each lane owns TPL contiguous ticks, in-lane serial
+//     sums plus a wave64 DPP scan give D and S, a DPP max plus a ballot gives the lowest tick of
+//     maximal volume, and the fill uses the closed form
+//        fill_bid(q) = min(D(q), V*) - min(D(q+1), V*),  fill_ask(q) = min(S(q), V*) - min(S(q-1), V*).
+//     No cross-wave scan pass and only two barriers per step; the clearing wave rotates with the
+//     step so the clearing work spreads over the CU's four SIMDs.
+//   * Books are uint32 (exact integers; a host-side guard proves no overflow), stored in LDS as
+//     interleaved (bid, ask) pairs so the clearing wave reads a tick with one 64-bit access.
+//   * The order generator is Philox4x32-10 with counter (step, agent, market, 0): the first round
+//     multiplies only the step and market words, so the products of rounds 1-3 that do not depend
+//     on the agent are computed once per step in scalar registers.
+//   * Work items (one market, or several equal-size markets sharing a workgroup in lock-step) are
+//     claimed from an on-device queue in longest-first order, so markets of uneven size run in a
+//     single launch; the last workgroup to finish resets the queue for the next launch.
+//   * HBM is read when an item starts (book + state) and written when it ends: traffic per launch
+//     is independent of S.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "cae.h"
+
+namespace {
+
+// ------------------------------------------------------------------------------------------
+// Device-side data (workspace layout is private to this file).
+// ------------------------------------------------------------------------------------------
+struct DevMarket {
+    uint32_t L, A, K, Q;
+    uint32_t n_noise, n_mom, h, tpl;  // tpl: ticks per lane of the clearing wave (power of 2)
+    uint64_t book_off;                // word offset of bid[0]; ask[0] is at book_off + L
+    uint64_t pad;
+};
+static_assert(sizeof(DevMarket) == 48, "DevMarket layout");
+
+struct Item {
+    uint32_t first;     // index into the market order list
+    uint32_t count;     // markets in this item
+    uint32_t wpm_log2;  // log2(waves per market)
+    uint32_t stride;    // LDS words per market slice (book pairs + 8 scratch words)
+};
+
+struct EngineArgs {
+    const DevMarket *desc;
+    const uint32_t *order;
+    const Item *items;
+    uint32_t *ctr;  // [0] next item, [1] finished claimers
+    uint32_t *book;
+    cae_state *state;
+    const double *lnT;  // lnT[n] = ln(n), n in [0, 2048]
+    uint32_t n_items;
+    uint32_t n_claimers;
+    uint32_t S;
+    uint32_t k0, k1;
+};
+
+constexpr uint32_t kM0 = 0xD2511F53u;
+constexpr uint32_t kM1 = 0xCD9E8D57u;
+constexpr uint32_t kW0 = 0x9E3779B9u;
+constexpr uint32_t kW1 = 0xBB67AE85u;
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+
+// a ^ b ^ c in one gfx950 VALU op (v_bitop3_b32 with the truth table of a three-way xor)
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
+__device__ __forceinline__ void mulhilo(uint32_t m, uint32_t x, uint32_t &hi, uint32_t &lo)
+{
+    const uint64_t p = (uint64_t)m * (uint64_t)x;
+    hi = (uint32_t)(p >> 32);
+    lo = (uint32_t)p;
+}
+
+// Philox4x32-10 for counter (s, a, m, 0) and key (k0, k1), split into the part that is the same
+// for every agent of a market-step (rounds 1-3 without the agent word) and the per-agent rest.
+struct PhiloxStep {
+    uint32_t ua, ux3k, uz0, uz2, z3, k0, k1;
+
+    __device__ __forceinline__ PhiloxStep(uint32_t s, uint32_t m, uint32_t key0, uint32_t key1)
+    {
+        uint32_t h0, l0, h1, l1;
+        // round 1 (key k): products of the step and market words
+        mulhilo(kM0, s, h0, l0);
+        mulhilo(kM1, m, h1, l1);
+        ua = h1 ^ key0;  // x0 = ua ^ a
+        const uint32_t x1 = l1, x2 = h0 ^ key1, x3 = l0;
+        // round 2 (key k + W): the x2 product is agent-independent
+        mulhilo(kM1, x2, h1, l1);
+        const uint32_t y0 = h1 ^ x1 ^ (key0 + kW0);
+        const uint32_t y1 = l1;
+        ux3k = x3 ^ (key1 + kW1);  // y2 = hi(M0 x0) ^ ux3k, y3 = lo(M0 x0)
+        // round 3 (key k + 2W): the y0 product is agent-independent
+        mulhilo(kM0, y0, h0, l0);
+        uz0 = y1 ^ (key0 + 2u * kW0);  // z0 = hi(M1 y2) ^ uz0, z1 = lo(M1 y2)
+        uz2 = h0 ^ (key1 + 2u * kW1);  // z2 = uz2 ^ y3
+        z3 = l0;
+        k0 = key0;
+        k1 = key1;
+    }
+
+    __device__ __forceinline__ void words(uint32_t a, uint32_t &w0, uint32_t &w1, uint32_t &w2) const
+    {
+        uint32_t h, l;
+        mulhilo(kM0, ua ^ a, h, l);
+        const uint32_t y2 = h ^ ux3k, y3 = l;
+        mulhilo(kM1, y2, h, l);
+        uint32_t c0 = h ^ uz0, c1 = l, c2 = uz2 ^ y3, c3 = z3;
+#pragma unroll
+        for (uint32_t r = 3; r < 10; ++r) {  // rounds 4..10 use key k + r W
+            uint32_t h0, l0, h1, l1;
+            mulhilo(kM0, c0, h0, l0);
+            mulhilo(kM1, c2, h1, l1);
+            c0 = xor3(h1, c1, k0 + r * kW0);
+            c2 = xor3(h0, c3, k1 + r * kW1);
+            c1 = l1;
+            c3 = l0;
+        }
+        w0 = c0;
+        w1 = c1;
+        w2 = c2;
+    }
+};
+
+// ------------------------------------------------------------------------------------------
+// wave64 primitives (GFX9 DPP: row_shr within 16-lane rows, row_bcast:15/31 across rows).
+// ------------------------------------------------------------------------------------------
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ uint32_t dpp(uint32_t x)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROW_MASK, 0xf, false);
+}
+
+__device__ __forceinline__ uint32_t wave_scan_add(uint32_t x)  // inclusive
+{
+    x += dpp<0x111, 0xf>(x);
+    x += dpp<0x112, 0xf>(x);
+    x += dpp<0x114, 0xf>(x);
+    x += dpp<0x118, 0xf>(x);
+    x += dpp<0x142, 0xa>(x);
+    x += dpp<0x143, 0xc>(x);
+    return x;
+}
+
+__device__ __forceinline__ uint32_t wave_max(uint32_t x)  // uniform result
+{
+    x = max(x, dpp<0x111, 0xf>(x));
+    x = max(x, dpp<0x112, 0xf>(x));
+    x = max(x, dpp<0x114, 0xf>(x));
+    x = max(x, dpp<0x118, 0xf>(x));
+    x = max(x, dpp<0x142, 0xa>(x));
+    x = max(x, dpp<0x143, 0xc>(x));
+    return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
+}
+
+__device__ __forceinline__ uint32_t readlane(uint32_t x, uint32_t l)
+{
+    return (uint32_t)__builtin_amdgcn_readlane((int)x, (int)l);
+}
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
+// Orders LDS traffic of one wave with respect to itself (LDS executes one wave's accesses in
+// issue order; this only keeps the compiler from moving accesses across the point).
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+struct ClearOut {
+    uint32_t p, v, bb, ba;  // clearing tick, volume, best bid / best ask after the fill (kNone: empty)
+};
+
+// Clears one book with one wave.  bk: LDS pairs (bid, ask) for ticks [0, 64*TPL), zero beyond L.
+// Lane l owns ticks [l*TPL, l*TPL + TPL).  Result is wave-uniform.
+template <int TPL>
+__device__ __forceinline__ ClearOut clear_wave(uint32_t *__restrict__ bk, uint32_t lane)
+{
+    uint32_t b[TPL], k[TPL];
+    const uint32_t q0 = lane * TPL;
+    if constexpr (TPL == 1) {
+        const uint2 v = reinterpret_cast<const uint2 *>(bk)[q0];
+        b[0] = v.x;
+        k[0] = v.y;
+    } else {
+#pragma unroll
+        for (int j = 0; j < TPL / 2; ++j) {
+            const uint4 v = reinterpret_cast<const uint4 *>(bk)[(q0 >> 1) + j];
+            b[2 * j] = v.x;
+            k[2 * j] = v.y;
+            b[2 * j + 1] = v.z;
+            k[2 * j + 1] = v.w;
+        }
+    }
+    uint32_t sb = 0, sa = 0;
+#pragma unroll
+    for (int j = 0; j < TPL; ++j) {
+        sb += b[j];
+        sa += k[j];
+    }
+    const uint32_t ib = wave_scan_add(sb);
+    const uint32_t ia = wave_scan_add(sa);
+    const uint32_t Tb = readlane(ib, 63);  // all bids
+    const uint32_t eb = ib - sb;          // bids on ticks below this lane's first tick
+    const uint32_t ea = ia - sa;          // asks on ticks below this lane's first tick
+
+    // V(q) = min(D(q), S(q)); D(q) = Tb - bids below q; S(q) = asks at or below q
+    uint32_t best = 0, bestq = 0;
+    {
+        uint32_t cb = eb, ca = ea;
+#pragma unroll
+        for (int j = 0; j < TPL; ++j) {
+            const uint32_t D = Tb - cb;
+            ca += k[j];
+            const uint32_t V = min(D, ca);
+            if (V > best) {
+                best = V;
+                bestq = q0 + j;
+            }
+            cb += b[j];
+        }
+    }
+    ClearOut out;
+    out.v = wave_max(best);
+    out.p = 0;
+    if (out.v != 0) {
+        const uint32_t vs = out.v;
+        const uint64_t mk = ballot(best == vs);
+        out.p = readlane(bestq, (uint32_t)__builtin_ctzll(mk));  // lowest tick of maximal volume
+        uint32_t cb = eb, ca = ea;
+        bool changed = false;
+#pragma unroll
+        for (int j = 0; j < TPL; ++j) {
+            const uint32_t D = Tb - cb;
+            const uint32_t Dn = D - b[j];
+            const uint32_t Sp = ca;
+            const uint32_t Sq = ca + k[j];
+            const uint32_t fb = min(D, vs) - min(Dn, vs);
+            const uint32_t fs = min(Sq, vs) - min(Sp, vs);
+            cb += b[j];
+            ca += k[j];
+            b[j] -= fb;
+            k[j] -= fs;
+            changed |= (fb | fs) != 0;
+        }
+        if (changed) {
+            if constexpr (TPL == 1) {
+                reinterpret_cast<uint2 *>(bk)[q0] = make_uint2(b[0], k[0]);
+            } else {
+#pragma unroll
+                for (int j = 0; j < TPL / 2; ++j)
+                    reinterpret_cast<uint4 *>(bk)[(q0 >> 1) + j] =
+                        make_uint4(b[2 * j], k[2 * j], b[2 * j + 1], k[2 * j + 1]);
+            }
+        }
+    }
+    uint32_t hb = kNone, la = kNone;
+#pragma unroll
+    for (int j = 0; j < TPL; ++j)
+        if (b[j] != 0) hb = q0 + j;
+#pragma unroll
+    for (int j = TPL - 1; j >= 0; --j)
+        if (k[j] != 0) la = q0 + j;
+    const uint64_t mb = ballot(hb != kNone);
+    const uint64_t ma = ballot(la != kNone);
+    out.bb = mb ? readlane(hb, 63u - (uint32_t)__builtin_clzll(mb)) : kNone;
+    out.ba = ma ? readlane(la, (uint32_t)__builtin_ctzll(ma)) : kNone;
+    return out;
+}
+
+template <int TPL_MAX>
+__device__ __forceinline__ ClearOut clear_dispatch(uint32_t *bk, uint32_t tpl, uint32_t lane)
+{
+    if constexpr (TPL_MAX >= 16) {
+        if (tpl == 16) return clear_wave<16>(bk, lane);
+    }
+    if constexpr (TPL_MAX >= 8) {
+        if (tpl == 8) return clear_wave<8>(bk, lane);
+    }
+    if constexpr (TPL_MAX >= 4) {
+        if (tpl == 4) return clear_wave<4>(bk, lane);
+    }
+    if constexpr (TPL_MAX >= 2) {
+        if (tpl == 2) return clear_wave<2>(bk, lane);
+    }
+    return clear_wave<1>(bk, lane);
+}
+
+// Every order of one market-step, added into the LDS book (interleaved pairs: word 2*tick+side).
+__device__ __forceinline__ void gen_orders(const DevMarket &d, uint32_t m, uint32_t s,
+                                           uint32_t last, uint32_t prev, uint32_t key0,
+                                           uint32_t key1, uint32_t t, uint32_t nthr, uint32_t *bk)
+{
+    const PhiloxStep ph(s, m, key0, key1);
+    const int base = (int)last - (int)d.K;
+    const uint32_t span = 2u * d.K + 1u;
+    const uint32_t Q = d.Q;
+    const int top = (int)d.L - 1;
+    uint32_t a = t;
+    for (; a < d.n_noise; a += nthr) {
+        uint32_t w0, w1, w2;
+        ph.words(a, w0, w1, w2);
+        const int tick = min(max(base + (int)__umulhi(w1, span), 0), top);
+        const uint32_t q = 1u + __umulhi(w2, Q);
+        atomicAdd(&bk[2u * (uint32_t)tick + (w0 >> 31)], q);
+    }
+    if (a < d.A) {
+        const uint32_t mom_end = d.n_noise + d.n_mom;
+        const int h = (int)d.h;
+        for (; a < d.A; a += nthr) {
+            uint32_t w0, w1, w2;
+            ph.words(a, w0, w1, w2);
+            uint32_t sell;
+            int tick;
+            if (a < mom_end) {  // MOMENTUM
+                sell = last > prev ? 0u : (last < prev ? 1u : (w0 >> 31));
+                tick = (int)last + (sell ? -1 : 1);
+            } else {  // MAKER
+                sell = (a ^ s) & 1u;
+                tick = (int)last + (sell ? h : -h);
+            }
+            tick = min(max(tick, 0), top);
+            const uint32_t q = 1u + __umulhi(w2, Q);
+            atomicAdd(&bk[2u * (uint32_t)tick + sell], q);
+        }
+    }
+}
+
+// One market (or an idle slot of a lock-step item) for all S steps.  MULTI: the market spans
+// several waves and the workgroup barrier separates the phases (Algorithm 1's barriers).
+template <int TPL_MAX, bool MULTI>
+__device__ __forceinline__ void run_market(const EngineArgs &args, const Item &item, uint32_t sub,
+                                           uint32_t w_in, uint32_t lane, bool active,
+                                           uint32_t *lds)
+{
+    const uint32_t wpm_mask = (1u << item.wpm_log2) - 1u;
+    const uint32_t nthr = 64u << item.wpm_log2;
+    const uint32_t t = (w_in << 6) | lane;
+    uint32_t *bk = lds + sub * item.stride;
+    uint32_t *scr = bk + item.stride - 8u;
+
+    uint32_t m = 0;
+    DevMarket d{};
+    uint32_t last = 0, prev = 0;
+    uint64_t steps0 = 0, n_trade = 0, sum_vol = 0, sum_px = 0, sum_spread = 0, n_spread = 0;
+    double sum_r = 0.0, sum_r2 = 0.0;
+    if (active) {
+        m = args.order[item.first + sub];
+        d = args.desc[m];
+        const cae_state *st = args.state + m;
+        last = st->last;
+        prev = st->prev;
+        steps0 = st->steps_done;
+        n_trade = st->n_trade;
+        sum_vol = st->sum_vol;
+        sum_px = st->sum_px;
+        sum_spread = st->sum_spread;
+        n_spread = st->n_spread;
+        sum_r = st->sum_r;
+        sum_r2 = st->sum_r2;
+        const uint32_t *gb = args.book + d.book_off;
+        const uint32_t padded = 64u * d.tpl;
+        for (uint32_t q = t; q < padded; q += nthr) {
+            uint2 v = make_uint2(0u, 0u);
+            if (q < d.L) {
+                v.x = gb[q];
+                v.y = gb[d.L + q];
+            }
+            reinterpret_cast<uint2 *>(bk)[q] = v;
+        }
+    }
+    if constexpr (MULTI) __syncthreads();
+    else wave_sync();
+
+    const double *lnT = args.lnT + d.L;  // ln(L + tick)
+    for (uint32_t i = 0; i < args.S; ++i) {
+        const uint32_t s = (uint32_t)steps0 + i;
+        if (active) gen_orders(d, m, s, last, prev, args.k0, args.k1, t, nthr, bk);
+        if constexpr (MULTI) __syncthreads();
+        else wave_sync();
+        ClearOut co;
+        if (active && w_in == (i & wpm_mask)) {
+            co = clear_dispatch<TPL_MAX>(bk, d.tpl, lane);
+            if constexpr (MULTI) {
+                if (lane == 0) *reinterpret_cast<uint4 *>(scr) = make_uint4(co.p, co.v, co.bb, co.ba);
+            }
+        }
+        if constexpr (MULTI) __syncthreads();
+        else wave_sync();
+        if (active) {
+            if constexpr (MULTI) {
+                const uint4 r = *reinterpret_cast<const uint4 *>(scr);
+                co.p = (uint32_t)__builtin_amdgcn_readfirstlane((int)r.x);
+                co.v = (uint32_t)__builtin_amdgcn_readfirstlane((int)r.y);
+                co.bb = (uint32_t)__builtin_amdgcn_readfirstlane((int)r.z);
+                co.ba = (uint32_t)__builtin_amdgcn_readfirstlane((int)r.w);
+            }
+            prev = last;
+            if (co.v != 0) {
+                last = co.p;
+                n_trade += 1;
+                sum_vol += co.v;
+                sum_px += co.p;
+            }
+            if (co.bb != kNone && co.ba != kNone) {
+                sum_spread += (uint64_t)(co.ba - co.bb);
+                n_spread += 1;
+            }
+            const double r = lnT[last] - lnT[prev];
+            sum_r = sum_r + r;
+            sum_r2 = sum_r2 + r * r;
+        }
+    }
+    if (active) {
+        uint32_t *gb = args.book + d.book_off;
+        for (uint32_t q = t; q < d.L; q += nthr) {
+            const uint2 v = reinterpret_cast<const uint2 *>(bk)[q];
+            gb[q] = v.x;
+            gb[d.L + q] = v.y;
+        }
+        if (t == 0) {
+            cae_state *st = args.state + m;
+            st->last = last;
+            st->prev = prev;
+            st->steps_done = steps0 + args.S;
+            st->n_trade = n_trade;
+            st->sum_vol = sum_vol;
+            st->sum_px = sum_px;
+            st->sum_spread = sum_spread;
+            st->n_spread = n_spread;
+            st->sum_r = sum_r;
+            st->sum_r2 = sum_r2;
+        }
+    }
+}
+
+template <int TPL_MAX>
+__global__ void __launch_bounds__(1024) cae_engine_kernel(const EngineArgs args)
+{
+    extern __shared__ __align__(16) uint32_t lds[];
+    __shared__ uint32_t s_claim;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = tid & 63u;
+    const uint32_t wave = tid >> 6;
+    for (;;) {
+        if (tid == 0) s_claim = atomicAdd(args.ctr, 1u);
+        __syncthreads();
+        const uint32_t it = s_claim;
+        __syncthreads();
+        if (it >= args.n_items) break;
+        const Item item = args.items[it];
+        const uint32_t sub = wave >> item.wpm_log2;
+        const uint32_t w_in = wave & ((1u << item.wpm_log2) - 1u);
+        const bool active = sub < item.count;
+        if (item.wpm_log2 == 0) {
+            if (active) run_market<TPL_MAX, false>(args, item, sub, w_in, lane, true, lds);
+        } else {
+            run_market<TPL_MAX, true>(args, item, sub, w_in, lane, active, lds);
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        // the last claimer to finish leaves the queue at zero for the next launch
+        const uint32_t done = atomicAdd(args.ctr + 1, 1u);
+        if (done == args.n_claimers - 1u) {
+            atomicExch(args.ctr, 0u);
+            atomicExch(args.ctr + 1, 0u);
+        }
+    }
+}
+
+// One clearing pass over n books of L ticks: one wave per book, four books per workgroup.
+template <int TPL>
+__global__ void __launch_bounds__(256) cae_clear_kernel(uint32_t L, uint32_t n, uint32_t *book,
+                                                        uint32_t *pstar, uint32_t *vstar)
+{
+    extern __shared__ __align__(16) uint32_t lds[];
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wave = threadIdx.x >> 6;
+    const uint32_t i = blockIdx.x * 4u + wave;
+    if (i >= n) return;
+    uint32_t *bk = lds + wave * (2u * 64u * TPL);
+    uint32_t *gb = book + (uint64_t)i * 2u * L;
+    for (uint32_t q = lane; q < 64u * TPL; q += 64u) {
+        uint2 v = make_uint2(0u, 0u);
+        if (q < L) {
+            v.x = gb[q];
+            v.y = gb[L + q];
+        }
+        reinterpret_cast<uint2 *>(bk)[q] = v;
+    }
+    wave_sync();
+    const ClearOut co = clear_wave<TPL>(bk, lane);
+    wave_sync();
+    for (uint32_t q = lane; q < L; q += 64u) {
+        const uint2 v = reinterpret_cast<const uint2 *>(bk)[q];
+        gb[q] = v.x;
+        gb[L + q] = v.y;
+    }
+    if (lane == 0) {
+        pstar[i] = co.p;
+        vstar[i] = co.v;
+    }
+}
+
+__global__ void cae_fill_kernel(uint32_t *p, uint64_t n, uint32_t v)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// ------------------------------------------------------------------------------------------
+// Host side.
+// ------------------------------------------------------------------------------------------
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess) return fail(CAE_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr uint32_t kVersion = 1;
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+uint32_t tpl_for(uint32_t L)
+{
+    uint32_t t = 1;
+    while (64u * t < L) t <<= 1;
+    return t;
+}
+
+uint32_t lclass(uint32_t L)
+{
+    uint32_t c = 0;
+    while (c < 4 && (64u << c) < L) ++c;
+    return c;
+}
+
+uint32_t aclass(uint32_t A)
+{
+    uint32_t lg = 31u - (uint32_t)__builtin_clz(A);
+    lg = std::min(std::max(lg, 6u), 13u);
+    return lg - 6u;
+}
+
+int validate(const cae_market *desc, uint32_t M)
+{
+    if (!desc) return fail(CAE_EINVAL, "desc is NULL");
+    if (M == 0) return fail(CAE_EINVAL, "M must be >= 1");
+    for (uint32_t m = 0; m < M; ++m) {
+        const cae_market &d = desc[m];
+        if (d.L < 1 || d.L > 1024) return fail(CAE_EINVAL, "market %u: L=%u outside 1..1024", m, d.L);
+        if (d.A < 1) return fail(CAE_EINVAL, "market %u: A must be >= 1", m);
+        if (d.K > (1u << 30)) return fail(CAE_EINVAL, "market %u: K=%u too large", m, d.K);
+        if (d.Q < 1) return fail(CAE_EINVAL, "market %u: Q must be >= 1", m);
+        if ((uint64_t)d.A * d.Q >= (1ull << 32)) return fail(CAE_EINVAL, "market %u: A*Q >= 2^32", m);
+        if ((uint64_t)d.n_noise + d.n_mom > d.A)
+            return fail(CAE_EINVAL, "market %u: n_noise + n_mom > A", m);
+        if (d.maker_half_spread >= d.L) return fail(CAE_EINVAL, "market %u: maker_half_spread >= L", m);
+        if (d.flags != 0) return fail(CAE_EINVAL, "market %u: flags must be 0", m);
+    }
+    return CAE_OK;
+}
+
+struct Layout {
+    size_t off_desc, off_order, off_items, off_ctr, off_lnt, total;
+};
+
+Layout layout_for(uint32_t M)
+{
+    Layout l;
+    size_t o = 0;
+    l.off_desc = o;
+    o = align_up(o + sizeof(DevMarket) * (size_t)M, kAlign);
+    l.off_order = o;
+    o = align_up(o + sizeof(uint32_t) * (size_t)M, kAlign);
+    l.off_items = o;
+    o = align_up(o + sizeof(Item) * (size_t)M, kAlign);
+    l.off_ctr = o;
+    o = align_up(o + 4 * sizeof(uint32_t), kAlign);
+    l.off_lnt = o;
+    o = align_up(o + sizeof(double) * 2049, kAlign);
+    l.total = o;
+    return l;
+}
+
+int device_cus(int dev, uint32_t *num_cu)
+{
+    int v = 0;
+    HIP_TRY(hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev));
+    *num_cu = (uint32_t)v;
+    return CAE_OK;
+}
+
+using EngineFn = void (*)(const EngineArgs);
+
+EngineFn engine_fn(uint32_t tpl_max)
+{
+    switch (tpl_max) {
+    case 1: return cae_engine_kernel<1>;
+    case 2: return cae_engine_kernel<2>;
+    case 4: return cae_engine_kernel<4>;
+    case 8: return cae_engine_kernel<8>;
+    default: return cae_engine_kernel<16>;
+    }
+}
+
+uint32_t auto_wpm(uint32_t L, uint32_t A)
+{
+    (void)L;
+    // about 8 agents per lane per step, at most 16 waves
+    uint32_t w = 1;
+    while (w < 16 && 64u * 8u * (2u * w) <= A) w <<= 1;
+    return w;
+}
+
+}  // namespace
+
+struct cae_ensemble {
+    int device = 0;
+    uint32_t M = 0;
+    uint64_t seed = 0;
+    hipStream_t stream = nullptr;
+    cae_buffers dev{};
+    std::vector<cae_market> desc;
+    std::vector<uint64_t> steps_done;
+    uint64_t book_words = 0;
+    Layout lay{};
+    uint32_t n_items = 0, tpl_max = 1, waves_per_group = 1, lds_bytes = 0, grid = 0;
+    cae_tuning tuning{};
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    bool have_timing = false;
+};
+
+namespace {
+
+// Build the work list: markets of equal (waves per market, ticks per lane) are packed into
+// items that fill a workgroup; items run longest first.
+int build_schedule(cae_ensemble *e, const cae_tuning *tn, std::vector<DevMarket> &dm,
+                   std::vector<uint32_t> &order, std::vector<Item> &items)
+{
+    const uint32_t M = e->M;
+    cae_tuning t{};
+    if (tn) t = *tn;
+    std::vector<uint32_t> wpm(M);
+    uint32_t wpm_max = 1, tpl_max = 1;
+    for (uint32_t m = 0; m < M; ++m) {
+        const cae_market &d = e->desc[m];
+        const uint32_t c = lclass(d.L) * 8u + aclass(d.A);
+        uint32_t w = t.waves_per_market[c];
+        if (w == 0) w = auto_wpm(d.L, d.A);
+        if (w > 16 || (w & (w - 1)) != 0) return fail(CAE_EINVAL, "waves_per_market[%u]=%u not a power of 2 <= 16", c, w);
+        wpm[m] = w;
+        t.waves_per_market[c] = (uint8_t)w;
+        wpm_max = std::max(wpm_max, w);
+        tpl_max = std::max(tpl_max, tpl_for(d.L));
+    }
+    uint32_t G = t.waves_per_group;
+    if (G == 0) G = std::max(wpm_max, 4u);
+    if (G > 16 || G < wpm_max) return fail(CAE_EINVAL, "waves_per_group=%u must be in [max waves_per_market=%u, 16]", G, wpm_max);
+    uint32_t lds_budget = t.max_lds_bytes ? t.max_lds_bytes : 64u * 1024u;
+    if (lds_budget > 160u * 1024u) lds_budget = 160u * 1024u;
+
+    // LPT cost: per step, agent work plus clearing work (the clearing wave touches 64*tpl ticks)
+    std::vector<double> cost(M);
+    for (uint32_t m = 0; m < M; ++m) {
+        const cae_market &d = e->desc[m];
+        cost[m] = (double)d.A + 8.0 * 64.0 * tpl_for(d.L) / 4.0 + 256.0;
+    }
+    order.resize(M);
+    for (uint32_t m = 0; m < M; ++m) order[m] = m;
+    const bool keep = (t.flags & 1u) != 0;
+    if (!keep)
+        std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return cost[a] > cost[b]; });
+
+    // open bins per (wpm, tpl)
+    struct Bin { std::vector<uint32_t> ms; uint32_t wpm, tpl; };
+    std::vector<Bin> open;
+    std::vector<std::pair<double, Bin>> done;
+    for (uint32_t idx = 0; idx < M; ++idx) {
+        const uint32_t m = order[idx];
+        const uint32_t w = wpm[m], tp = tpl_for(e->desc[m].L);
+        const uint32_t stride = 2u * 64u * tp + 8u;
+        uint32_t cap = G / w;
+        cap = std::max(1u, std::min(cap, lds_budget / (stride * 4u)));
+        Bin *b = nullptr;
+        for (auto &x : open)
+            if (x.wpm == w && x.tpl == tp) b = &x;
+        if (!b) {
+            open.push_back(Bin{{}, w, tp});
+            b = &open.back();
+        }
+        b->ms.push_back(m);
+        if (b->ms.size() == cap) {
+            double c = 0;
+            for (uint32_t mm : b->ms) c = std::max(c, cost[mm]);
+            done.push_back({c, *b});
+            b->ms.clear();
+        }
+    }
+    for (auto &b : open)
+        if (!b.ms.empty()) {
+            double c = 0;
+            for (uint32_t mm : b.ms) c = std::max(c, cost[mm]);
+            done.push_back({c, b});
+        }
+    if (!keep)
+        std::stable_sort(done.begin(), done.end(), [](const auto &a, const auto &b) { return a.first > b.first; });
+
+    order.clear();
+    items.clear();
+    uint32_t lds_max = 0;
+    for (auto &p : done) {
+        const Bin &b = p.second;
+        Item it;
+        it.first = (uint32_t)order.size();
+        it.count = (uint32_t)b.ms.size();
+        it.wpm_log2 = (uint32_t)__builtin_ctz(b.wpm);
+        it.stride = 2u * 64u * b.tpl + 8u;
+        for (uint32_t mm : b.ms) order.push_back(mm);
+        items.push_back(it);
+        lds_max = std::max(lds_max, it.count * it.stride * 4u);
+    }
+
+    // device descriptors
+    dm.resize(M);
+    uint64_t off = 0;
+    for (uint32_t m = 0; m < M; ++m) {
+        const cae_market &d = e->desc[m];
+        DevMarket x{};
+        x.L = d.L; x.A = d.A; x.K = d.K; x.Q = d.Q;
+        x.n_noise = d.n_noise; x.n_mom = d.n_mom; x.h = d.maker_half_spread;
+        x.tpl = tpl_for(d.L);
+        x.book_off = off;
+        off += 2ull * d.L;
+        dm[m] = x;
+    }
+    t.waves_per_group = G;
+    t.max_lds_bytes = lds_budget;
+    e->tuning = t;
+    e->n_items = (uint32_t)items.size();
+    e->tpl_max = tpl_max;
+    e->waves_per_group = G;
+    e->lds_bytes = lds_max;
+
+    uint32_t ncu = 0;
+    int rc = device_cus(e->device, &ncu);
+    if (rc) return rc;
+    int per_cu = 0;
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(engine_fn(tpl_max)),
+                                                         (int)(G * 64u), (size_t)lds_max));
+    if (per_cu < 1) return fail(CAE_EINVAL, "schedule does not fit on a CU (lds %u B, %u waves)", lds_max, G);
+    if (t.groups_per_cu) per_cu = std::min<int>(per_cu, (int)t.groups_per_cu);
+    e->tuning.groups_per_cu = (uint32_t)per_cu;
+    e->grid = std::min<uint32_t>(e->n_items, ncu * (uint32_t)per_cu);
+    return CAE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *cae_strerror(int code)
+{
+    switch (code) {
+    case CAE_OK: return "ok";
+    case CAE_EINVAL: return "invalid argument";
+    case CAE_EOVERFLOW: return "book could overflow 32 bits";
+    case CAE_ENOSPACE: return "buffer too small";
+    case CAE_EHIP: return "HIP runtime error";
+    case CAE_ESTATE: return "invalid state";
+    default: return "unknown error";
+    }
+}
+
+const char *cae_last_error(void) { return g_err.c_str(); }
+
+int cae_device_info(uint32_t *num_cu, uint32_t *version)
+{
+    if (version) *version = kVersion;
+    if (num_cu) {
+        int dev = 0;
+        HIP_TRY(hipGetDevice(&dev));
+        return device_cus(dev, num_cu);
+    }
+    return CAE_OK;
+}
+
+int cae_sizes(const cae_market *desc, uint32_t M, cae_sizes_t *out)
+{
+    if (!out) return fail(CAE_EINVAL, "out is NULL");
+    int rc = validate(desc, M);
+    if (rc) return rc;
+    uint64_t words = 0;
+    for (uint32_t m = 0; m < M; ++m) words += 2ull * desc[m].L;
+    out->book_words = words;
+    out->book_bytes = 4ull * words;
+    out->state_bytes = (uint64_t)M * sizeof(cae_state);
+    out->workspace_bytes = layout_for(M).total;
+    return CAE_OK;
+}
+
+int cae_create(const cae_market *desc, uint32_t M, uint64_t seed, const cae_buffers *dev,
+               void *stream, const cae_tuning *tuning, cae_ensemble **out)
+{
+    if (!out || !dev || !dev->book || !dev->state || !dev->workspace)
+        return fail(CAE_EINVAL, "NULL handle or device buffer");
+    *out = nullptr;
+    int rc = validate(desc, M);
+    if (rc) return rc;
+    cae_ensemble *e = new cae_ensemble();
+    HIP_TRY(hipGetDevice(&e->device));
+    e->M = M;
+    e->seed = seed;
+    e->stream = (hipStream_t)stream;
+    e->dev = *dev;
+    e->desc.assign(desc, desc + M);
+    e->steps_done.assign(M, 0);
+    e->lay = layout_for(M);
+    for (uint32_t m = 0; m < M; ++m) e->book_words += 2ull * desc[m].L;
+
+    std::vector<DevMarket> dm;
+    std::vector<uint32_t> order;
+    std::vector<Item> items;
+    rc = build_schedule(e, tuning, dm, order, items);
+    if (rc) {
+        delete e;
+        return rc;
+    }
+    std::vector<unsigned char> ws(e->lay.total, 0);
+    std::memcpy(ws.data() + e->lay.off_desc, dm.data(), sizeof(DevMarket) * M);
+    std::memcpy(ws.data() + e->lay.off_order, order.data(), sizeof(uint32_t) * M);
+    std::memcpy(ws.data() + e->lay.off_items, items.data(), sizeof(Item) * items.size());
+    std::vector<double> lnt(2049, 0.0);
+    for (int n = 1; n <= 2048; ++n) lnt[n] = std::log((double)n);
+    std::memcpy(ws.data() + e->lay.off_lnt, lnt.data(), sizeof(double) * 2049);
+    std::vector<cae_state> st(M);
+    for (uint32_t m = 0; m < M; ++m) {
+        std::memset(&st[m], 0, sizeof(cae_state));
+        st[m].last = desc[m].L / 2;
+        st[m].prev = desc[m].L / 2;
+    }
+    auto cleanup = [&](int code) {
+        delete e;
+        return code;
+    };
+    hipError_t he;
+    he = hipMemcpyAsync(dev->workspace, ws.data(), ws.size(), hipMemcpyHostToDevice, e->stream);
+    if (he == hipSuccess)
+        he = hipMemcpyAsync(dev->state, st.data(), sizeof(cae_state) * M, hipMemcpyHostToDevice, e->stream);
+    if (he == hipSuccess) {
+        const uint32_t blocks = (uint32_t)std::min<uint64_t>((e->book_words + 255) / 256, 4096);
+        hipLaunchKernelGGL(cae_fill_kernel, dim3(blocks), dim3(256), 0, e->stream, dev->book, e->book_words, 0u);
+        he = hipGetLastError();
+    }
+    if (he == hipSuccess) he = hipStreamSynchronize(e->stream);
+    if (he == hipSuccess) he = hipEventCreate(&e->ev0);
+    if (he == hipSuccess) he = hipEventCreate(&e->ev1);
+    if (he != hipSuccess) return cleanup(fail(CAE_EHIP, "create: %s", hipGetErrorString(he)));
+    *out = e;
+    return CAE_OK;
+}
+
+int cae_step(cae_ensemble *e, uint32_t S)
+{
+    if (!e) return fail(CAE_EINVAL, "NULL ensemble");
+    if (S == 0) return CAE_OK;
+    for (uint32_t m = 0; m < e->M; ++m) {
+        const unsigned __int128 tot = (unsigned __int128)(e->steps_done[m] + S) * e->desc[m].A * e->desc[m].Q;
+        if (tot >= ((unsigned __int128)1 << 32))
+            return fail(CAE_EOVERFLOW, "market %u: (steps_done + S) * A * Q >= 2^32", m);
+    }
+    HIP_TRY(hipSetDevice(e->device));
+    unsigned char *ws = static_cast<unsigned char *>(e->dev.workspace);
+    EngineArgs a;
+    a.desc = reinterpret_cast<const DevMarket *>(ws + e->lay.off_desc);
+    a.order = reinterpret_cast<const uint32_t *>(ws + e->lay.off_order);
+    a.items = reinterpret_cast<const Item *>(ws + e->lay.off_items);
+    a.ctr = reinterpret_cast<uint32_t *>(ws + e->lay.off_ctr);
+    a.book = e->dev.book;
+    a.state = e->dev.state;
+    a.lnT = reinterpret_cast<const double *>(ws + e->lay.off_lnt);
+    a.n_items = e->n_items;
+    a.n_claimers = e->grid;
+    a.S = S;
+    a.k0 = (uint32_t)e->seed;
+    a.k1 = (uint32_t)(e->seed >> 32);
+    HIP_TRY(hipEventRecord(e->ev0, e->stream));
+    hipLaunchKernelGGL(engine_fn(e->tpl_max), dim3(e->grid), dim3(e->waves_per_group * 64u), e->lds_bytes,
+                       e->stream, a);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipEventRecord(e->ev1, e->stream));
+    e->have_timing = true;
+    for (uint32_t m = 0; m < e->M; ++m) e->steps_done[m] += S;
+    return CAE_OK;
+}
+
+int cae_last_step_ms(cae_ensemble *e, float *ms)
+{
+    if (!e || !ms) return fail(CAE_EINVAL, "NULL argument");
+    if (!e->have_timing) return fail(CAE_ESTATE, "no step has been launched");
+    HIP_TRY(hipEventSynchronize(e->ev1));
+    HIP_TRY(hipEventElapsedTime(ms, e->ev0, e->ev1));
+    return CAE_OK;
+}
+
+int cae_read_books(cae_ensemble *e, uint32_t *host_book, uint64_t n_words)
+{
+    if (!e || !host_book) return fail(CAE_EINVAL, "NULL argument");
+    if (n_words < e->book_words) return fail(CAE_ENOSPACE, "need %llu words", (unsigned long long)e->book_words);
+    HIP_TRY(hipSetDevice(e->device));
+    HIP_TRY(hipMemcpyAsync(host_book, e->dev.book, 4ull * e->book_words, hipMemcpyDeviceToHost, e->stream));
+    HIP_TRY(hipStreamSynchronize(e->stream));
+    return CAE_OK;
+}
+
+int cae_read_state(cae_ensemble *e, cae_state *host_state, uint32_t M)
+{
+    if (!e || !host_state) return fail(CAE_EINVAL, "NULL argument");
+    if (M < e->M) return fail(CAE_ENOSPACE, "need %u states", e->M);
+    HIP_TRY(hipSetDevice(e->device));
+    HIP_TRY(hipMemcpyAsync(host_state, e->dev.state, sizeof(cae_state) * e->M, hipMemcpyDeviceToHost, e->stream));
+    HIP_TRY(hipStreamSynchronize(e->stream));
+    return CAE_OK;
+}
+
+int cae_write_state(cae_ensemble *e, const cae_state *host_state, uint32_t M, const uint32_t *host_book,
+                    uint64_t n_words)
+{
+    if (!e || !host_state || !host_book) return fail(CAE_EINVAL, "NULL argument");
+    if (M != e->M) return fail(CAE_EINVAL, "M=%u does not match the ensemble (%u)", M, e->M);
+    if (n_words != e->book_words)
+        return fail(CAE_EINVAL, "n_words=%llu does not match the ensemble (%llu)", (unsigned long long)n_words,
+                    (unsigned long long)e->book_words);
+    for (uint32_t m = 0; m < M; ++m) {
+        if (host_state[m].last >= e->desc[m].L || host_state[m].prev >= e->desc[m].L)
+            return fail(CAE_EINVAL, "market %u: last/prev outside the grid", m);
+        const unsigned __int128 tot = (unsigned __int128)host_state[m].steps_done * e->desc[m].A * e->desc[m].Q;
+        if (tot >= ((unsigned __int128)1 << 32)) return fail(CAE_EINVAL, "market %u: steps_done past the guard", m);
+    }
+    HIP_TRY(hipSetDevice(e->device));
+    HIP_TRY(hipMemcpyAsync(e->dev.state, host_state, sizeof(cae_state) * M, hipMemcpyHostToDevice, e->stream));
+    HIP_TRY(hipMemcpyAsync(e->dev.book, host_book, 4ull * n_words, hipMemcpyHostToDevice, e->stream));
+    HIP_TRY(hipStreamSynchronize(e->stream));
+    for (uint32_t m = 0; m < M; ++m) e->steps_done[m] = host_state[m].steps_done;
+    return CAE_OK;
+}
+
+int cae_get_tuning(const cae_ensemble *e, cae_tuning *out)
+{
+    if (!e || !out) return fail(CAE_EINVAL, "NULL argument");
+    *out = e->tuning;
+    return CAE_OK;
+}
+
+int cae_destroy(cae_ensemble *e)
+{
+    if (!e) return CAE_OK;
+    if (e->ev0) (void)hipEventDestroy(e->ev0);
+    if (e->ev1) (void)hipEventDestroy(e->ev1);
+    delete e;
+    return CAE_OK;
+}
+
+int cae_clear(uint32_t L, uint32_t M, uint32_t *dev_book, uint32_t *dev_pstar, uint32_t *dev_vstar, void *stream)
+{
+    if (L < 1 || L > 1024) return fail(CAE_EINVAL, "L=%u outside 1..1024", L);
+    if (!dev_book || !dev_pstar || !dev_vstar) return fail(CAE_EINVAL, "NULL device pointer");
+    if (M == 0) return CAE_OK;
+    const uint32_t tpl = tpl_for(L);
+    const dim3 grid((M + 3u) / 4u), block(256);
+    const size_t lds = 4u * 2u * 64u * tpl * 4u;
+    hipStream_t s = (hipStream_t)stream;
+    switch (tpl) {
+    case 1: hipLaunchKernelGGL(cae_clear_kernel<1>, grid, block, lds, s, L, M, dev_book, dev_pstar, dev_vstar); break;
+    case 2: hipLaunchKernelGGL(cae_clear_kernel<2>, grid, block, lds, s, L, M, dev_book, dev_pstar, dev_vstar); break;
+    case 4: hipLaunchKernelGGL(cae_clear_kernel<4>, grid, block, lds, s, L, M, dev_book, dev_pstar, dev_vstar); break;
+    case 8: hipLaunchKernelGGL(cae_clear_kernel<8>, grid, block, lds, s, L, M, dev_book, dev_pstar, dev_vstar); break;
+    default: hipLaunchKernelGGL(cae_clear_kernel<16>, grid, block, lds, s, L, M, dev_book, dev_pstar, dev_vstar); break;
+    }
+    HIP_TRY(hipGetLastError());
+    return CAE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,227 @@
+"""GPU engine vs CPU oracle: bit-exact books, states and integer statistics; floating-point
+statistics within 1e-6 relative (they are computed in the same order from the same table, so
+in practice they are bit-equal too).  Every call goes through the C ABI."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2606_21784_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+INT_FIELDS = ["last", "prev", "steps_done", "n_trade", "sum_vol", "sum_px", "sum_spread",
+              "n_spread"]
+
+
+def _engine():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2606_21784_amd import engine
+    return engine
+
+
+def _run_gpu(descs, seed, steps, tuning=None):
+    E = _engine()
+    ens = E.Ensemble(descs, seed, tuning=tuning)
+    for S in steps:
+        ens.step(S)
+    st, bk = ens.read_state(), ens.read_books()
+    tn = ens.tuning()
+    ens.close()
+    return st, bk, tn
+
+
+def _assert_states(gpu, ref, rtol=1e-6):
+    for f in INT_FIELDS:
+        np.testing.assert_array_equal(gpu[f], ref[f], err_msg=f)
+    for f in ("sum_r", "sum_r2"):
+        np.testing.assert_allclose(gpu[f], ref[f], rtol=rtol, atol=1e-300, err_msg=f)
+
+
+def _assert_books(descs, gpu_book, ref_book, ids=None):
+    L = descs["L"].astype(np.int64)
+    off = np.zeros(len(L), np.int64)
+    off[1:] = np.cumsum(2 * L)[:-1]
+    if ids is None:
+        np.testing.assert_array_equal(gpu_book, ref_book)
+        return
+    roff = 0
+    for i in ids:
+        n = 2 * int(L[i])
+        np.testing.assert_array_equal(gpu_book[off[i]:off[i] + n], ref_book[roff:roff + n],
+                                      err_msg="market %d" % i)
+        roff += n
+
+
+def test_smoke_workload_full():
+    w = W.smoke()
+    st, bk, _ = _run_gpu(w["descs"], w["seed"], [w["S"]])
+    rst, rbk = O.run(w["descs"], w["seed"], w["S"])
+    _assert_books(w["descs"], bk, rbk)
+    _assert_states(st, rst)
+    assert (st["sum_r"] == rst["sum_r"]).all() and (st["sum_r2"] == rst["sum_r2"]).all()
+
+
+@pytest.mark.parametrize("wpm,G", [(1, 1), (1, 4), (2, 2), (2, 8), (4, 4), (8, 8), (16, 16)])
+def test_schedule_invariance(wpm, G):
+    """Every waves-per-market / waves-per-workgroup choice gives the oracle's books."""
+    descs = W.uniform(6, 64, 128, 8, 10)
+    tn = {"waves_per_group": G, "waves_per_market": {c: wpm for c in range(40)}}
+    st, bk, used = _run_gpu(descs, 0, [60], tuning=tn)
+    assert used["waves_per_group"] == G
+    rst, rbk = O.run(descs, 0, 60)
+    _assert_books(descs, bk, rbk)
+    _assert_states(st, rst)
+
+
+@pytest.mark.parametrize("cfg", [
+    # L, A, K, Q, n_noise, n_mom, h  -- ragged sizes, one-lane grids, mixed agent classes
+    (1, 1, 0, 1, 1, 0, 0),
+    (3, 65, 2, 7, 65, 0, 1),
+    (100, 1000, 9, 33, 500, 300, 3),
+    (257, 777, 16, 100, 300, 300, 5),
+    (1000, 130, 40, 5, 0, 130, 7),
+    (1024, 3000, 64, 100, 1000, 1000, 2),
+    (64, 64, 8, 10, 0, 0, 2),
+])
+def test_ragged_and_mixed_markets(cfg):
+    L, A, K, Q, nn, nm, h = cfg
+    descs = W.uniform(5, L, A, K, Q, n_noise=nn, n_mom=nm, h=h)
+    st, bk, _ = _run_gpu(descs, 12345, [40])
+    rst, rbk = O.run(descs, 12345, 40)
+    _assert_books(descs, bk, rbk)
+    _assert_states(st, rst)
+
+
+def test_mixed_sizes_one_launch():
+    rng = np.random.default_rng(7)
+    n = 40
+    L = rng.choice([1, 17, 64, 100, 128, 256, 300, 512, 1000, 1024], n)
+    A = rng.integers(1, 3000, n)
+    d = np.zeros(n, W.MARKET_DTYPE)
+    d["L"], d["A"], d["K"], d["Q"] = L, A, np.maximum(1, L // 16), rng.integers(1, 101, n)
+    d["n_noise"] = A // 2
+    d["n_mom"] = A // 4
+    d["h"] = np.minimum(2, L - 1)
+    st, bk, _ = _run_gpu(d, 99, [30])
+    rst, rbk = O.run(d, 99, 30)
+    _assert_books(d, bk, rbk)
+    _assert_states(st, rst)
+
+
+def test_step_split_and_resume():
+    E = _engine()
+    descs = W.uniform(8, 128, 300, 8, 20, n_noise=200, n_mom=50)
+    rst, rbk = O.run(descs, 5, 100)
+    ens = E.Ensemble(descs, 5)
+    ens.step(37)
+    mid_st, mid_bk = ens.read_state(), ens.read_books()
+    ens.step(63)
+    _assert_books(descs, ens.read_books(), rbk)
+    _assert_states(ens.read_state(), rst)
+    # checkpoint resume into a fresh ensemble
+    ens2 = E.Ensemble(descs, 5)
+    ens2.write_state(mid_st, mid_bk)
+    ens2.step(63)
+    _assert_books(descs, ens2.read_books(), rbk)
+    _assert_states(ens2.read_state(), rst)
+    ens.close()
+    ens2.close()
+
+
+def test_overflow_guard_refuses_launch():
+    E = _engine()
+    from paper_2606_21784_amd import _lib
+    descs = W.uniform(2, 64, 2**16, 4, 2**15)  # 2^31 per step
+    ens = E.Ensemble(descs, 0)
+    ens.step(1)
+    with pytest.raises(_lib.CaeError) as ei:
+        ens.step(1)
+    assert ei.value.code == _lib.CAE_EOVERFLOW
+    st = ens.read_state()
+    assert (st["steps_done"] == 1).all()
+    ens.close()
+
+
+def test_write_state_rejects_bad_input():
+    E = _engine()
+    from paper_2606_21784_amd import _lib
+    descs = W.uniform(2, 64, 16, 4, 5)
+    ens = E.Ensemble(descs, 0)
+    st, bk = ens.read_state(), ens.read_books()
+    bad = st.copy()
+    bad["last"][0] = 64
+    with pytest.raises(_lib.CaeError):
+        ens.write_state(bad, bk)
+    with pytest.raises(_lib.CaeError):
+        ens.write_state(st[:1], bk)
+    with pytest.raises(_lib.CaeError):
+        ens.write_state(st, bk[:-1])
+    ens.close()
+
+
+def test_clear_worked_example_and_random_books():
+    import json
+    import os
+    import torch
+    E = _engine()
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "worked_example_l5.json")))
+    book = torch.tensor(g["BUY"] + g["SELL"], dtype=torch.int32, device="cuda")
+    ps, vs = E.clear_books(book, 5, 1)
+    torch.cuda.synchronize()
+    assert int(ps[0]) == g["p_star"] and int(vs[0]) == g["volume"]
+    res = book.cpu().numpy()
+    assert res[:5].tolist() == g["new_bid"] and res[5:].tolist() == g["new_ask"]
+    rng = np.random.default_rng(11)
+    for L in (1, 2, 5, 63, 64, 65, 128, 200, 256, 511, 512, 1000, 1024):
+        n = 37
+        books = rng.integers(0, 60, size=(n, 2, L)).astype(np.uint32)
+        books[::3] = 0  # empty books
+        books[1::5, 0, : L // 2] = 0  # one-sided
+        rp, rv, rres = O.clear_batch(books)
+        dev = torch.from_numpy(books.reshape(-1).view(np.int32).copy()).cuda()
+        ps, vs = E.clear_books(dev, L, n)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(ps.cpu().numpy().view(np.uint32), rp)
+        np.testing.assert_array_equal(vs.cpu().numpy().view(np.uint32).astype(np.uint64), rv)
+        np.testing.assert_array_equal(dev.cpu().numpy().view(np.uint32).reshape(n, 2, L), rres)
+
+
+def test_fixed_workload_full_parity():
+    """The fixed workload at full size (1024 x 1024 agents x 1000 steps, L = 256) in the launch
+    configuration the benchmark times; every market against the oracle."""
+    w = W.fixed()
+    st, bk, _ = _run_gpu(w["descs"], w["seed"], [w["S"]])
+    rst, rbk = O.run(w["descs"], w["seed"], w["S"])
+    _assert_books(w["descs"], bk, rbk)
+    _assert_states(st, rst)
+
+
+@pytest.mark.slow
+def test_market_sweep_sampled():
+    """Market-count sweep at its full step count (10000 steps, L = 512, A = 4096), smallest
+    and a mid-size M; sampled markets re-simulated alone by the oracle."""
+    for M in (16, 1024):
+        w = W.market_sweep(M)
+        st, bk, _ = _run_gpu(w["descs"], w["seed"], [w["S"]])
+        ids = [0, M // 2, M - 1]
+        rst, rbk = O.run(w["descs"][ids], w["seed"], w["S"], ids=ids)
+        _assert_books(w["descs"], bk, rbk, ids=ids)
+        _assert_states(st[ids], rst)
+
+
+@pytest.mark.slow
+def test_uneven_ensemble_sampled():
+    w = W.uneven()
+    d = w["descs"]
+    st, bk, _ = _run_gpu(d, w["seed"], [w["S"]])
+    A = d["A"].astype(np.int64)
+    rng = np.random.default_rng(1)
+    ids = sorted(set([int(np.argmax(A)), int(np.argmin(A))] +
+                     rng.choice(len(d), 10, replace=False).tolist()))
+    rst, rbk = O.run(d[ids], w["seed"], w["S"], ids=ids)
+    _assert_books(d, bk, rbk, ids=ids)
+    _assert_states(st[ids], rst)
+    # every market traded at least once and no book is crossed
+    assert (st["n_trade"] > 0).all()
