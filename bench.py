@@ -1,0 +1,195 @@
+#!/usr/bin/env python3
+"""Throughput of the persistent call-auction engine on one MI355X.
+
+One benchmark step = one cae_step call of S = 1000 steps over the fixed standard workload
+(1024 markets, L = 256 ticks, A = 1024 agents, offsets +-16, quantities 1..100, seed 1):
+1.049e9 agent events, every row of the hot path (orders, aggregation, curves, clearing,
+allocation, statistics, persistent loop) inside one launch.  Inputs are resident on the GPU
+before timing starts.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--copy-calib]
+
+Prints ONE JSON line on stdout (diagnostics go to stderr).
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "agent events/s on 1 MI355X + roofline %; surrogate vs exact sweep speedup at ≤5% err"
+
+# --- roofline of the engine kernel (plain integer ALU work) --------------------------------
+# Peak: 256 CUs x 4 SIMDs x 16 lanes = 64 lane-slots per CU per clock at the 2.4 GHz peak
+# engine clock, for full-rate 32-bit VALU operations.
+N_CU, LANES_PER_CU, CLOCK_HZ = 256, 64, 2.4e9
+PEAK_SLOTS = N_CU * LANES_PER_CU * CLOCK_HZ  # 3.93e13 slots/s
+# Issue cost in full-rate slots on gfx950, measured at saturation by
+# paper_2606_21784_amd/ubench.py (one workgroup of 16 waves per CU, wave64 instructions per clock
+# per CU): v_add/v_xor/v_bitop3 1.0, v_mul_hi_u32 1/0.824 = 1.21, v_mad_u64_u32 1/0.792 = 1.26.
+COST = {"mad_u64_u32": 1.26, "mul_hi_u32": 1.21, "alu": 1.0}
+# Algorithmic work per agent event, from the generator and order rules (not from compiled
+# code): Philox4x32-10 with counter (step, agent, market, 0) needs 16 agent-dependent
+# 32x32->64 products and 18 agent-dependent three-input xors; 2 multiply-high range
+# reductions; 5 ops to form the tick (add, clamp), the quantity and the book address.
+# Clearing costs 10 ops per tick per step, i.e. 10 L / A per event.
+PHILOX_PRODUCTS, PHILOX_XORS, RANGE_MULHI, ORDER_OPS, CLEAR_OPS_PER_TICK = 16, 18, 2, 5, 10
+
+
+def slots_per_event(L, A):
+    return (PHILOX_PRODUCTS * COST["mad_u64_u32"] + PHILOX_XORS * COST["alu"]
+            + RANGE_MULHI * COST["mul_hi_u32"] + ORDER_OPS * COST["alu"]
+            + CLEAR_OPS_PER_TICK * COST["alu"] * L / A)
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "engine_fixed_M1024_L256_A1024_S1000.traffic.txt")
+KERNEL_SRC = os.path.join(ROOT, "paper_2606_21784_amd", "csrc", "cae_engine.hip")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_sha():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or None when the
+    kernel source changed after the counters were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha") != kernel_source_sha():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(w, n_markets):
+    import numpy as np
+
+    import oracle
+    descs = w["descs"][:n_markets]
+    nthreads = min(os.cpu_count() or 1, 16)
+    t0 = time.perf_counter()
+    st, bk = oracle.run(descs, w["seed"], w["S"], nthreads=nthreads)
+    dt = time.perf_counter() - t0
+    ev = float(np.sum(descs["A"].astype(np.float64))) * w["S"]
+    return {"value": ev / dt, "unit": "agent-events/s", "cores": nthreads, "kind": "oracle",
+            "sample": "%d of %d markets of %s, all %d steps (%.3g events, %.1f s wall)" %
+                      (n_markets, len(w["descs"]), w["name"], w["S"], ev, dt)}, st, bk
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--cpu-markets", type=int, default=1024)
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="after timing, copy 1 GiB device-to-device (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this engine has no multi-GPU path (markets would be "
+              "sharded with no communication); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2606_21784_amd import engine, workloads
+    assert torch.cuda.is_available(), "bench.py needs the GPU"
+    torch.cuda.set_device(0)
+
+    w = workloads.fixed()
+    d = w["descs"]
+    M, L, A, S = len(d), int(d["L"][0]), int(d["A"][0]), w["S"]
+    events = float(np.sum(d["A"].astype(np.float64))) * S
+    ens = engine.Ensemble(d, w["seed"])
+    sched = ens.tuning()
+    sched = {"waves_per_group": sched["waves_per_group"], "groups_per_cu": sched["groups_per_cu"],
+             "waves_per_market": sorted(set(sched["waves_per_market"].values()))}
+    log("schedule:", json.dumps(sched))
+
+    for _ in range(args.warmup):
+        ens.step(S)
+    torch.cuda.synchronize()
+    snap_st, snap_bk = ens.read_state(), ens.read_books()
+    guard = (2**32 - 1) // (A * int(d["Q"][0]))
+
+    kern_ms = []
+    wall = 0.0
+    done = 0
+    while done < args.steps:
+        chunk = min(args.steps - done, max(1, guard // S - args.warmup - 1))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(chunk):
+            ens.step(S)
+            kern_ms.append(ens.last_step_ms())
+        torch.cuda.synchronize()
+        wall += time.perf_counter() - t0
+        done += chunk
+        if done < args.steps:  # rewind outside the timed region (32-bit book guard)
+            ens.write_state(snap_st, snap_bk)
+    value = events * args.steps / wall
+    kms = sum(kern_ms) / len(kern_ms)
+    log("wall %.3f ms/step, kernel %.3f ms (min %.3f), %.4g events/s" %
+        (1e3 * wall / args.steps, kms, min(kern_ms), value))
+
+    if args.copy_calib:
+        x = torch.empty(1 << 28, dtype=torch.int32, device="cuda")
+        y = torch.empty_like(x)
+        x.fill_(1)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        log("copy calibration: 1 GiB read + 1 GiB written")
+
+    w_ev = slots_per_event(L, A)
+    achieved = events * w_ev / (kms * 1e-3)
+    traffic = measured_traffic()
+    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12,
+            "unit": "Tslot/s", "frac": achieved / PEAK_SLOTS, "traffic": traffic,
+            "kernel": "cae_engine_kernel<4>", "kernel_ms": kms,
+            "slots_per_event": w_ev, "events_per_launch": events,
+            "roofline_events_per_s": PEAK_SLOTS / w_ev}
+
+    result = {
+        "metric": METRIC, "value": value, "unit": "agent-events/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * wall / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": w["name"], "markets": M, "L": L, "A": A,
+                   "steps_per_call": S, "K": int(d["K"][0]), "Q": int(d["Q"][0]),
+                   "seed": w["seed"], "events_per_step": events, "parallelism": "none",
+                   "schedule": sched},
+        "roofline": roof,
+    }
+    if not args.no_cpu:
+        cb, rst, rbk = cpu_baseline(w, args.cpu_markets)
+        result["cpu_baseline"] = cb
+        # the benchmarked kernel is the correct one: its first call matches the oracle
+        n = args.cpu_markets
+        if args.warmup >= 1:
+            ok = np.array_equal(snap_bk[:n * 2 * L], rbk) if args.warmup == 1 else None
+            result["cpu_baseline"]["gpu_matches_oracle"] = ok
+    ens.close()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -9,6 +9,8 @@ ROOT = os.path.dirname(HERE)
 SOURCES = [os.path.join(HERE, "csrc", "cae_engine.hip")]
 EXTRA = [os.path.join(HERE, "csrc", "cae_mlp.hip")]
 LIB = os.path.join(HERE, "libcae.so")
+UBENCH_SRC = os.path.join(HERE, "csrc", "cae_ubench.hip")
+UBENCH_LIB = os.path.join(HERE, "libcae_ubench.so")
 ARCH = "gfx950"
 
 
@@ -16,8 +18,9 @@ def hipcc():
     return shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 
 
-def command(out):
-    srcs = SOURCES + [s for s in EXTRA if os.path.exists(s)]
+def command(out, srcs=None):
+    if srcs is None:
+        srcs = SOURCES + [s for s in EXTRA if os.path.exists(s)]
     return [hipcc(), "-O3", "-std=c++17", "--offload-arch=" + ARCH, "-fPIC", "-shared",
             "-ffp-contract=off",
             # packed fp32 VALU forms are kept out of every kernel
@@ -32,6 +35,12 @@ def build(verbose=False):
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
+    tmp = UBENCH_LIB + ".tmp%d" % os.getpid()
+    cmd = command(tmp, [UBENCH_SRC])
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, UBENCH_LIB)
     return LIB
 
 

@@ -460,11 +460,13 @@ __global__ void __launch_bounds__(1024) cae_engine_kernel(const EngineArgs args)
     __shared__ uint32_t s_claim;
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & 63u;
-    const uint32_t wave = tid >> 6;
+    // wave index made provably wave-uniform, so everything derived from it (market, descriptor,
+    // state, the per-step generator rounds) lives in scalar registers
+    const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane((int)(tid >> 6));
     for (;;) {
         if (tid == 0) s_claim = atomicAdd(args.ctr, 1u);
         __syncthreads();
-        const uint32_t it = s_claim;
+        const uint32_t it = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_claim);
         __syncthreads();
         if (it >= args.n_items) break;
         const Item item = args.items[it];
