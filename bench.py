@@ -92,6 +92,68 @@ def cpu_baseline(w, n_markets):
                       (n_markets, len(w["descs"]), w["name"], w["S"], ev, dt)}, st, bk
 
 
+def uneven_leg(reps=2):
+    """Markets of uneven L and A in one autotuned persistent launch, against one launch per
+    size class (same kernel, same market streams) on the same stream."""
+    import numpy as np
+    import torch
+
+    from paper_2606_21784_amd import autotune, engine, workloads
+    w = workloads.uneven()
+    d, S = w["descs"], w["S"]
+    events = float(d["A"].astype(np.float64).sum()) * S
+
+    def timed(ensembles, n):
+        """Best wall time of n rounds; each round rewinds the ensembles to their opening state
+        (outside the timed region) and launches S steps on every ensemble back to back."""
+        opening = [(e.read_state(), e.read_books()) for e in ensembles]
+        best = None
+        for _ in range(n):
+            for e, (st, bk) in zip(ensembles, opening):
+                e.write_state(st, bk)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for e in ensembles:
+                e.step(S)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            best = dt if best is None else min(best, dt)
+        return best
+
+    t0 = time.perf_counter()
+    tn = autotune.tune(d, seed=w["seed"], S_probe=40, log=log)
+    tune_s = time.perf_counter() - t0
+    ens = engine.Ensemble(d, w["seed"], tuning=tn)
+    t_batched = timed([ens], reps)
+    sched = ens.tuning()
+    ens.close()
+    ens = engine.Ensemble(d, w["seed"])
+    t_default = timed([ens], reps)
+    ens.close()
+    groups = autotune.per_size_groups(d)
+    parts = []
+    for c, idx in groups.items():
+        wpm = tn["waves_per_market"][c]
+        parts.append(engine.Ensemble(d[idx], w["seed"], market_ids=idx,
+                                     tuning={"waves_per_group": max(4, wpm),
+                                             "waves_per_market": {c: wpm}}))
+    t_split = timed(parts, reps)
+    for e in parts:
+        e.close()
+    out = {"workload": w["name"], "markets": len(d), "events": events,
+           "batched_ms": 1e3 * t_batched, "batched_events_per_s": events / t_batched,
+           "untuned_batched_ms": 1e3 * t_default,
+           "per_size_launches": len(groups), "per_size_ms": 1e3 * t_split,
+           "per_size_events_per_s": events / t_split, "speedup_vs_per_size": t_split / t_batched,
+           "schedule": {"waves_per_group": sched["waves_per_group"],
+                        "groups_per_cu": sched["groups_per_cu"],
+                        "waves_per_market": {str(k): v for k, v in sched["waves_per_market"].items()}},
+           "tune_s": tune_s}
+    log("uneven: batched %.1f ms (untuned %.1f), per-size %d launches %.1f ms" %
+        (out["batched_ms"], out["untuned_batched_ms"], len(groups), out["per_size_ms"]))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -99,6 +161,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-markets", type=int, default=1024)
+    ap.add_argument("--no-uneven", action="store_true",
+                    help="skip the uneven-ensemble leg (batched launch vs per-size launches)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="after timing, copy 1 GiB device-to-device (counter calibration)")
     args = ap.parse_args()
@@ -188,6 +252,8 @@ def main():
             ok = np.array_equal(snap_bk[:n * 2 * L], rbk) if args.warmup == 1 else None
             result["cpu_baseline"]["gpu_matches_oracle"] = ok
     ens.close()
+    if not args.no_uneven:
+        result["uneven"] = uneven_leg()
     print(json.dumps(result), flush=True)
 
 

@@ -113,6 +113,9 @@ typedef struct cae_tuning {
     uint32_t max_lds_bytes;                     /* LDS budget per workgroup               */
     uint32_t flags;                             /* bit 0: keep descriptor order (no LPT)  */
     uint8_t waves_per_market[CAE_NUM_CLASSES];  /* 1,2,4,8,16 per size class; 0 = auto    */
+    float class_cost[CAE_NUM_CLASSES];          /* relative cost of one market-step per
+                                                   class for the longest-first order;
+                                                   0 = the built-in model A + 2*64*TPL    */
 } cae_tuning;
 
 typedef struct cae_ensemble cae_ensemble;
@@ -135,10 +138,14 @@ int cae_sizes(const cae_market *desc, uint32_t M, cae_sizes_t *out);
  * and L ticks; section III-B: books start empty at the opening price).  Copies the
  * descriptors and schedule into dev->workspace, zeroes dev->book and writes the opening
  * state to dev->state, ordered on `stream`; returns after those copies completed.
- * tuning may be NULL (automatic schedule).  *out receives a host handle that owns only
- * host memory.  Errors: CAE_EINVAL (descriptor, M == 0, NULL pointer), CAE_EHIP. */
-int cae_create(const cae_market *desc, uint32_t M, uint64_t seed, const cae_buffers *dev,
-               void *stream, const cae_tuning *tuning, cae_ensemble **out);
+ * market_ids (host, M entries, may be NULL = 0..M-1) is the market index each market uses in
+ * the generator counter, so a subset of a larger ensemble (a shard, or one size group)
+ * reproduces that ensemble's markets bit for bit.  tuning may be NULL (automatic schedule).
+ * *out receives a host handle that owns only host memory.
+ * Errors: CAE_EINVAL (descriptor, M == 0, NULL pointer, bad tuning), CAE_EHIP. */
+int cae_create(const cae_market *desc, uint32_t M, uint64_t seed, const uint32_t *market_ids,
+               const cae_buffers *dev, void *stream, const cae_tuning *tuning,
+               cae_ensemble **out);
 
 /* Advance every market by S steps in one persistent launch on the ensemble's stream
  * (Algorithm 1: the S-step loop runs on the device; section III-E phases 2-5 each step).

@@ -38,7 +38,8 @@ class Buffers(C.Structure):
 class Tuning(C.Structure):
     _fields_ = [("waves_per_group", C.c_uint32), ("groups_per_cu", C.c_uint32),
                 ("max_lds_bytes", C.c_uint32), ("flags", C.c_uint32),
-                ("waves_per_market", C.c_uint8 * NUM_CLASSES)]
+                ("waves_per_market", C.c_uint8 * NUM_CLASSES),
+                ("class_cost", C.c_float * NUM_CLASSES)]
 
 
 class CaeError(RuntimeError):
@@ -68,7 +69,7 @@ def lib():
     L.cae_last_error.restype = C.c_char_p
     L.cae_device_info.argtypes = [P, P]
     L.cae_sizes.argtypes = [P, u32, P]
-    L.cae_create.argtypes = [P, u32, u64, P, P, P, P]
+    L.cae_create.argtypes = [P, u32, u64, P, P, P, P, P]
     L.cae_step.argtypes = [P, u32]
     L.cae_read_books.argtypes = [P, P, u64]
     L.cae_read_state.argtypes = [P, P, u32]

@@ -1,0 +1,126 @@
+"""Autotuner for the persistent engine's schedule.
+
+The engine's schedule has three knobs (``cae_tuning`` in include/cae.h):
+  * waves per market, per size class (class = L bucket x A bucket): how many wave64s generate
+    one market's orders; the rest of the workgroup's waves belong to other markets;
+  * waves per workgroup: how many markets of one class share a workgroup (in lock-step when a
+    market spans more than one wave) and therefore how the workgroup's LDS is partitioned into
+    market slices;
+  * the resident workgroups per CU that the persistent grid is sized for.
+
+``tune`` times candidates on the GPU through the C ABI (short launches on copies of the
+ensemble's own markets), keeps the fastest per class, then picks waves-per-workgroup on the
+whole ensemble.  Results can be cached as JSON keyed by GPU architecture and size class.
+"""
+import json
+import os
+import time
+
+import numpy as np
+
+from . import engine
+
+WPM_CANDIDATES = (1, 2, 4, 8, 16)
+GROUP_CANDIDATES = (4, 8, 16)
+
+
+def classes_of(descs):
+    return np.array([engine.size_class(int(L), int(A)) for L, A in zip(descs["L"], descs["A"])])
+
+
+def _time_launch(descs, seed, tuning, S, reps=2):
+    ens = engine.Ensemble(descs, seed, tuning=tuning)
+    try:
+        ens.step(S)
+        ens.last_step_ms()
+        best = None
+        for _ in range(reps):
+            ens.step(S)
+            ms = ens.last_step_ms()
+            best = ms if best is None else min(best, ms)
+        return best
+    finally:
+        ens.close()
+
+
+def _probe_set(descs, idx, min_markets, rng):
+    """Markets of one class for probing: the class's own descriptors, replicated or sampled so
+    that the probe fills the GPU (min_markets) without exceeding it by much."""
+    if len(idx) >= min_markets:
+        pick = np.sort(rng.choice(idx, min_markets, replace=False))
+    else:
+        pick = np.resize(idx, min_markets)
+    return np.ascontiguousarray(descs[pick])
+
+
+def tune(descs, seed=0, S_probe=40, min_markets=None, cache=None, arch="gfx950", log=None):
+    """Return a tuning dict for ``engine.Ensemble(..., tuning=...)``.
+
+    descs: the ensemble's market descriptors; S_probe: steps per timed probe launch;
+    min_markets: markets per class probe (default 4 per CU); cache: optional JSON path.
+    """
+    rng = np.random.default_rng(0)
+    cached = {}
+    if cache and os.path.exists(cache):
+        with open(cache) as f:
+            cached = json.load(f).get(arch, {})
+    if min_markets is None:
+        min_markets = 4 * engine.device_info()["num_cu"]
+    cls = classes_of(descs)
+    wpm = {}
+    cost = {}
+    t0 = time.perf_counter()
+    for c in sorted(set(cls.tolist())):
+        key = str(c)
+        if key in cached:
+            wpm[c] = int(cached[key]["waves_per_market"])
+            cost[c] = float(cached[key]["ns_per_market_step"])
+            continue
+        probe = _probe_set(descs, np.nonzero(cls == c)[0], min_markets, rng)
+        events = float(probe["A"].astype(np.float64).sum()) * S_probe
+        best = None
+        for w in WPM_CANDIDATES:
+            tn = {"waves_per_group": max(4, w), "waves_per_market": {int(c): w}}
+            ms = _time_launch(probe, seed, tn, S_probe)
+            if log:
+                log("class %2d (L<=%4d, A~2^%d) wpm %2d: %.3f ms, %.3g events/s" %
+                    (c, 64 << (c // 8), 6 + c % 8, w, ms, events / (ms * 1e-3)))
+            if best is None or ms < best[1]:
+                best = (w, ms)
+        wpm[c] = best[0]
+        # per market-step cost when the class fills the GPU alone
+        cost[c] = best[1] * 1e6 / (len(probe) * S_probe) * engine.device_info()["num_cu"]
+        cached[key] = {"waves_per_market": wpm[c], "ns_per_market_step": cost[c]}
+    # waves per workgroup on the whole ensemble
+    wmax = max(wpm.values())
+    best_g = None
+    for G in GROUP_CANDIDATES:
+        if G < wmax:
+            continue
+        tn = {"waves_per_group": G, "waves_per_market": {int(c): w for c, w in wpm.items()}}
+        ms = _time_launch(descs, seed, tn, max(4, S_probe // 4), reps=1)
+        if log:
+            log("waves_per_group %2d: %.3f ms" % (G, ms))
+        if best_g is None or ms < best_g[1]:
+            best_g = (G, ms)
+    if cache:
+        allc = {}
+        if os.path.exists(cache):
+            with open(cache) as f:
+                allc = json.load(f)
+        allc[arch] = cached
+        os.makedirs(os.path.dirname(os.path.abspath(cache)), exist_ok=True)
+        with open(cache, "w") as f:
+            json.dump(allc, f, indent=1, sort_keys=True)
+    result = {"waves_per_group": best_g[0],
+              "waves_per_market": {int(c): int(w) for c, w in wpm.items()},
+              "class_cost_ns": {int(c): float(v) for c, v in cost.items()},
+              "tune_seconds": time.perf_counter() - t0}
+    return result
+
+
+def per_size_groups(descs):
+    """Indices of the markets of each size class (the per-size-launch baseline runs one
+    launch per group)."""
+    cls = classes_of(descs)
+    return {int(c): np.nonzero(cls == c)[0] for c in sorted(set(cls.tolist()))}

@@ -45,7 +45,8 @@ struct DevMarket {
     uint32_t L, A, K, Q;
     uint32_t n_noise, n_mom, h, tpl;  // tpl: ticks per lane of the clearing wave (power of 2)
     uint64_t book_off;                // word offset of bid[0]; ask[0] is at book_off + L
-    uint64_t pad;
+    uint32_t id;                      // market index in the generator counter
+    uint32_t pad;
 };
 static_assert(sizeof(DevMarket) == 48, "DevMarket layout");
 
@@ -190,32 +191,58 @@ struct ClearOut {
     uint32_t p, v, bb, ba;  // clearing tick, volume, best bid / best ask after the fill (kNone: empty)
 };
 
-// Clears one book with one wave.  bk: LDS pairs (bid, ask) for ticks [0, 64*TPL), zero beyond L.
-// Lane l owns ticks [l*TPL, l*TPL + TPL).  Result is wave-uniform.
-template <int TPL>
-__device__ __forceinline__ ClearOut clear_wave(uint32_t *__restrict__ bk, uint32_t lane)
+// Reads / writes CH consecutive (bid, ask) pairs starting at tick q of an LDS book.
+template <int CH>
+__device__ __forceinline__ void load_pairs(const uint32_t *bk, uint32_t q, uint32_t (&b)[CH], uint32_t (&k)[CH])
 {
-    uint32_t b[TPL], k[TPL];
-    const uint32_t q0 = lane * TPL;
-    if constexpr (TPL == 1) {
-        const uint2 v = reinterpret_cast<const uint2 *>(bk)[q0];
+    if constexpr (CH == 1) {
+        const uint2 v = reinterpret_cast<const uint2 *>(bk)[q];
         b[0] = v.x;
         k[0] = v.y;
     } else {
 #pragma unroll
-        for (int j = 0; j < TPL / 2; ++j) {
-            const uint4 v = reinterpret_cast<const uint4 *>(bk)[(q0 >> 1) + j];
+        for (int j = 0; j < CH / 2; ++j) {
+            const uint4 v = reinterpret_cast<const uint4 *>(bk)[(q >> 1) + j];
             b[2 * j] = v.x;
             k[2 * j] = v.y;
             b[2 * j + 1] = v.z;
             k[2 * j + 1] = v.w;
         }
     }
-    uint32_t sb = 0, sa = 0;
+}
+
+template <int CH>
+__device__ __forceinline__ void store_pairs(uint32_t *bk, uint32_t q, const uint32_t (&b)[CH], const uint32_t (&k)[CH])
+{
+    if constexpr (CH == 1) {
+        reinterpret_cast<uint2 *>(bk)[q] = make_uint2(b[0], k[0]);
+    } else {
 #pragma unroll
-    for (int j = 0; j < TPL; ++j) {
-        sb += b[j];
-        sa += k[j];
+        for (int j = 0; j < CH / 2; ++j)
+            reinterpret_cast<uint4 *>(bk)[(q >> 1) + j] = make_uint4(b[2 * j], k[2 * j], b[2 * j + 1], k[2 * j + 1]);
+    }
+}
+
+// Clears one book with one wave.  bk: LDS pairs (bid, ask) for ticks [0, 64*TPL), zero beyond L.
+// Lane l owns ticks [l*TPL, l*TPL + TPL) and streams them from LDS in chunks of at most four
+// ticks per pass (sums; volumes; fill), so registers do not grow with L.  Wave-uniform result.
+template <int TPL>
+__device__ __forceinline__ ClearOut clear_wave(uint32_t *__restrict__ bk, uint32_t lane)
+{
+    constexpr int CH = TPL < 4 ? TPL : 4;
+    constexpr int NCH = TPL / CH;
+    const uint32_t q0 = lane * TPL;
+
+    uint32_t sb = 0, sa = 0;  // this lane's bid and ask totals
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+        uint32_t b[CH], k[CH];
+        load_pairs<CH>(bk, q0 + c * CH, b, k);
+#pragma unroll
+        for (int j = 0; j < CH; ++j) {
+            sb += b[j];
+            sa += k[j];
+        }
     }
     const uint32_t ib = wave_scan_add(sb);
     const uint32_t ia = wave_scan_add(sa);
@@ -228,58 +255,55 @@ __device__ __forceinline__ ClearOut clear_wave(uint32_t *__restrict__ bk, uint32
     {
         uint32_t cb = eb, ca = ea;
 #pragma unroll
-        for (int j = 0; j < TPL; ++j) {
-            const uint32_t D = Tb - cb;
-            ca += k[j];
-            const uint32_t V = min(D, ca);
-            if (V > best) {
-                best = V;
-                bestq = q0 + j;
+        for (int c = 0; c < NCH; ++c) {
+            uint32_t b[CH], k[CH];
+            load_pairs<CH>(bk, q0 + c * CH, b, k);
+#pragma unroll
+            for (int j = 0; j < CH; ++j) {
+                const uint32_t D = Tb - cb;
+                ca += k[j];
+                const uint32_t V = min(D, ca);
+                if (V > best) {
+                    best = V;
+                    bestq = q0 + c * CH + j;
+                }
+                cb += b[j];
             }
-            cb += b[j];
         }
     }
     ClearOut out;
     out.v = wave_max(best);
     out.p = 0;
-    if (out.v != 0) {
-        const uint32_t vs = out.v;
-        const uint64_t mk = ballot(best == vs);
-        out.p = readlane(bestq, (uint32_t)__builtin_ctzll(mk));  // lowest tick of maximal volume
+    if (out.v != 0) out.p = readlane(bestq, (uint32_t)__builtin_ctzll(ballot(best == out.v)));
+
+    // closed-form price-priority fill (all zero when V* = 0), then best bid / best ask
+    const uint32_t vs = out.v;
+    uint32_t hb = kNone, la = kNone;
+    {
         uint32_t cb = eb, ca = ea;
-        bool changed = false;
 #pragma unroll
-        for (int j = 0; j < TPL; ++j) {
-            const uint32_t D = Tb - cb;
-            const uint32_t Dn = D - b[j];
-            const uint32_t Sp = ca;
-            const uint32_t Sq = ca + k[j];
-            const uint32_t fb = min(D, vs) - min(Dn, vs);
-            const uint32_t fs = min(Sq, vs) - min(Sp, vs);
-            cb += b[j];
-            ca += k[j];
-            b[j] -= fb;
-            k[j] -= fs;
-            changed |= (fb | fs) != 0;
-        }
-        if (changed) {
-            if constexpr (TPL == 1) {
-                reinterpret_cast<uint2 *>(bk)[q0] = make_uint2(b[0], k[0]);
-            } else {
+        for (int c = 0; c < NCH; ++c) {
+            uint32_t b[CH], k[CH];
+            const uint32_t qc = q0 + c * CH;
+            load_pairs<CH>(bk, qc, b, k);
+            bool changed = false;
 #pragma unroll
-                for (int j = 0; j < TPL / 2; ++j)
-                    reinterpret_cast<uint4 *>(bk)[(q0 >> 1) + j] =
-                        make_uint4(b[2 * j], k[2 * j], b[2 * j + 1], k[2 * j + 1]);
+            for (int j = 0; j < CH; ++j) {
+                const uint32_t D = Tb - cb;
+                const uint32_t Sq = ca + k[j];
+                const uint32_t fb = min(D, vs) - min(D - b[j], vs);
+                const uint32_t fs = min(Sq, vs) - min(ca, vs);
+                cb += b[j];
+                ca = Sq;
+                b[j] -= fb;
+                k[j] -= fs;
+                changed |= (fb | fs) != 0;
+                if (b[j] != 0) hb = qc + j;
+                if (k[j] != 0 && la == kNone) la = qc + j;
             }
+            if (changed) store_pairs<CH>(bk, qc, b, k);
         }
     }
-    uint32_t hb = kNone, la = kNone;
-#pragma unroll
-    for (int j = 0; j < TPL; ++j)
-        if (b[j] != 0) hb = q0 + j;
-#pragma unroll
-    for (int j = TPL - 1; j >= 0; --j)
-        if (k[j] != 0) la = q0 + j;
     const uint64_t mb = ballot(hb != kNone);
     const uint64_t ma = ballot(la != kNone);
     out.bb = mb ? readlane(hb, 63u - (uint32_t)__builtin_clzll(mb)) : kNone;
@@ -394,7 +418,7 @@ __device__ __forceinline__ void run_market(const EngineArgs &args, const Item &i
     const double *lnT = args.lnT + d.L;  // ln(L + tick)
     for (uint32_t i = 0; i < args.S; ++i) {
         const uint32_t s = (uint32_t)steps0 + i;
-        if (active) gen_orders(d, m, s, last, prev, args.k0, args.k1, t, nthr, bk);
+        if (active) gen_orders(d, d.id, s, last, prev, args.k0, args.k1, t, nthr, bk);
         if constexpr (MULTI) __syncthreads();
         else wave_sync();
         ClearOut co;
@@ -672,8 +696,8 @@ namespace {
 
 // Build the work list: markets of equal (waves per market, ticks per lane) are packed into
 // items that fill a workgroup; items run longest first.
-int build_schedule(cae_ensemble *e, const cae_tuning *tn, std::vector<DevMarket> &dm,
-                   std::vector<uint32_t> &order, std::vector<Item> &items)
+int build_schedule(cae_ensemble *e, const cae_tuning *tn, const uint32_t *ids,
+                   std::vector<DevMarket> &dm, std::vector<uint32_t> &order, std::vector<Item> &items)
 {
     const uint32_t M = e->M;
     cae_tuning t{};
@@ -697,11 +721,15 @@ int build_schedule(cae_ensemble *e, const cae_tuning *tn, std::vector<DevMarket>
     uint32_t lds_budget = t.max_lds_bytes ? t.max_lds_bytes : 64u * 1024u;
     if (lds_budget > 160u * 1024u) lds_budget = 160u * 1024u;
 
-    // LPT cost: per step, agent work plus clearing work (the clearing wave touches 64*tpl ticks)
+    // LPT cost of one market-step: measured per class if given, else agent work plus the
+    // clearing wave's pass over 64*tpl ticks
     std::vector<double> cost(M);
     for (uint32_t m = 0; m < M; ++m) {
         const cae_market &d = e->desc[m];
-        cost[m] = (double)d.A + 8.0 * 64.0 * tpl_for(d.L) / 4.0 + 256.0;
+        const uint32_t c = lclass(d.L) * 8u + aclass(d.A);
+        const float cc = tn ? tn->class_cost[c] : 0.0f;
+        if (!(cc >= 0.0f)) return fail(CAE_EINVAL, "class_cost[%u] is negative or NaN", c);
+        cost[m] = cc > 0.0f ? (double)cc : (double)d.A + 2.0 * 64.0 * tpl_for(d.L);
     }
     order.resize(M);
     for (uint32_t m = 0; m < M; ++m) order[m] = m;
@@ -768,6 +796,7 @@ int build_schedule(cae_ensemble *e, const cae_tuning *tn, std::vector<DevMarket>
         x.n_noise = d.n_noise; x.n_mom = d.n_mom; x.h = d.maker_half_spread;
         x.tpl = tpl_for(d.L);
         x.book_off = off;
+        x.id = ids ? ids[m] : m;
         off += 2ull * d.L;
         dm[m] = x;
     }
@@ -836,8 +865,8 @@ int cae_sizes(const cae_market *desc, uint32_t M, cae_sizes_t *out)
     return CAE_OK;
 }
 
-int cae_create(const cae_market *desc, uint32_t M, uint64_t seed, const cae_buffers *dev,
-               void *stream, const cae_tuning *tuning, cae_ensemble **out)
+int cae_create(const cae_market *desc, uint32_t M, uint64_t seed, const uint32_t *market_ids,
+               const cae_buffers *dev, void *stream, const cae_tuning *tuning, cae_ensemble **out)
 {
     if (!out || !dev || !dev->book || !dev->state || !dev->workspace)
         return fail(CAE_EINVAL, "NULL handle or device buffer");
@@ -858,7 +887,7 @@ int cae_create(const cae_market *desc, uint32_t M, uint64_t seed, const cae_buff
     std::vector<DevMarket> dm;
     std::vector<uint32_t> order;
     std::vector<Item> items;
-    rc = build_schedule(e, tuning, dm, order, items);
+    rc = build_schedule(e, tuning, market_ids, dm, order, items);
     if (rc) {
         delete e;
         return rc;

@@ -58,6 +58,8 @@ def tuning_struct(t=None):
     ts.flags = int(t.get("flags", 0))
     for c, w in dict(t.get("waves_per_market", {})).items():
         ts.waves_per_market[int(c)] = int(w)
+    for c, v in dict(t.get("class_cost_ns", {})).items():
+        ts.class_cost[int(c)] = float(v)
     return ts
 
 
@@ -73,10 +75,12 @@ class Ensemble:
     """M independent markets stepped by the persistent engine.
 
     descs: structured array of MARKET_DTYPE (see ``markets``); seed: 64-bit generator key;
-    stream: a torch.cuda.Stream (default: the current stream); tuning: see ``tuning_struct``.
+    market_ids: generator market index of each market (default 0..M-1), so a subset of a larger
+    ensemble reproduces its markets; stream: a torch.cuda.Stream (default: the current stream);
+    tuning: see ``tuning_struct``.
     """
 
-    def __init__(self, descs, seed, stream=None, tuning=None, device=None):
+    def __init__(self, descs, seed, stream=None, tuning=None, device=None, market_ids=None):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("the call-auction engine needs a ROCm GPU")
@@ -96,7 +100,14 @@ class Ensemble:
             bufs = Buffers(self.book.data_ptr(), self.state.data_ptr(), self.workspace.data_ptr())
             h = C.c_void_p()
             ts = tuning_struct(tuning)
+            ids = None
+            if market_ids is not None:
+                ids = np.ascontiguousarray(market_ids, dtype=np.uint32)
+                if ids.shape != (self.M,):
+                    raise ValueError("market_ids must have one entry per market")
+            self.market_ids = ids
             check("cae_create", L_.cae_create(_p(self.descs), self.M, self.seed & (2**64 - 1),
+                                              _p(ids) if ids is not None else None,
                                               C.byref(bufs), C.c_void_p(self.stream.cuda_stream),
                                               C.byref(ts) if ts is not None else None,
                                               C.byref(h)))
@@ -140,7 +151,9 @@ class Ensemble:
         return {"waves_per_group": t.waves_per_group, "groups_per_cu": t.groups_per_cu,
                 "max_lds_bytes": t.max_lds_bytes, "flags": t.flags,
                 "waves_per_market": {c: int(t.waves_per_market[c])
-                                     for c in range(_lib.NUM_CLASSES) if t.waves_per_market[c]}}
+                                     for c in range(_lib.NUM_CLASSES) if t.waves_per_market[c]},
+                "class_cost_ns": {c: float(t.class_cost[c])
+                                  for c in range(_lib.NUM_CLASSES) if t.class_cost[c] > 0}}
 
     def book_offsets(self):
         L = self.descs["L"].astype(np.uint64)

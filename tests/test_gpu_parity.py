@@ -225,3 +225,76 @@ def test_uneven_ensemble_sampled():
     _assert_states(st[ids], rst)
     # every market traded at least once and no book is crossed
     assert (st["n_trade"] > 0).all()
+
+
+def test_per_size_launches_and_shards_match_one_batched_launch():
+    """Markets keep their generator index when split into per-size-class launches or shards, so
+    every split reproduces the single batched launch bit for bit (and the oracle)."""
+    E = _engine()
+    from paper_2606_21784_amd import autotune
+    w = W.uneven(M=300)
+    d = w["descs"].copy()
+    d["A"] = np.minimum(d["A"], 3000)
+    d["n_noise"] = d["A"] // 2
+    d["n_mom"] = d["A"] // 4
+    S = 60
+    ens = E.Ensemble(d, w["seed"])
+    ens.step(S)
+    st, bk = ens.read_state(), ens.read_books()
+    ens.close()
+    off = np.zeros(len(d), np.int64)
+    off[1:] = np.cumsum(2 * d["L"].astype(np.int64))[:-1]
+    groups = list(autotune.per_size_groups(d).values())
+    halves = [np.arange(0, 150), np.arange(150, 300)]
+    for split in (groups, halves):
+        for idx in split:
+            sub = E.Ensemble(d[idx], w["seed"], market_ids=idx)
+            sub.step(S)
+            sst, sbk = sub.read_state(), sub.read_books()
+            sub.close()
+            _assert_states(sst, st[idx])
+            pos = 0
+            for i in idx:
+                n = 2 * int(d["L"][i])
+                np.testing.assert_array_equal(sbk[pos:pos + n], bk[off[i]:off[i] + n])
+                pos += n
+    ids = [0, 7, 299]
+    rst, rbk = O.run(d[ids], w["seed"], S, ids=ids)
+    _assert_books(d, bk, rbk, ids=ids)
+    _assert_states(st[ids], rst)
+
+
+def test_autotuned_schedule_is_exact():
+    E = _engine()
+    from paper_2606_21784_amd import autotune
+    w = W.uneven(M=200)
+    d = w["descs"].copy()
+    d["A"] = np.minimum(d["A"], 2000)
+    d["n_noise"] = d["A"]
+    tn = autotune.tune(d, seed=w["seed"], S_probe=8, min_markets=64)
+    assert tn["waves_per_group"] in autotune.GROUP_CANDIDATES
+    assert set(tn["waves_per_market"].values()) <= set(autotune.WPM_CANDIDATES)
+    ens = E.Ensemble(d, w["seed"], tuning=tn)
+    used = ens.tuning()
+    assert used["waves_per_group"] == tn["waves_per_group"]
+    ens.step(25)
+    st, bk = ens.read_state(), ens.read_books()
+    ens.close()
+    rst, rbk = O.run(d, w["seed"], 25)
+    _assert_books(d, bk, rbk)
+    _assert_states(st, rst)
+
+
+def test_queue_resets_between_launches():
+    """Many short launches in a row (the on-device work queue is reset by the last workgroup of
+    each launch) give the same result as one long launch."""
+    E = _engine()
+    descs = W.uniform(50, 64, 96, 8, 10, n_noise=60, n_mom=20)
+    ens = E.Ensemble(descs, 3, tuning={"waves_per_group": 4, "groups_per_cu": 1})
+    for _ in range(20):
+        ens.step(3)
+    st, bk = ens.read_state(), ens.read_books()
+    ens.close()
+    rst, rbk = O.run(descs, 3, 60)
+    _assert_books(descs, bk, rbk)
+    _assert_states(st, rst)
