@@ -187,6 +187,61 @@ int cae_destroy(cae_ensemble *e);
 int cae_clear(uint32_t L, uint32_t M, uint32_t *dev_book, uint32_t *dev_pstar,
               uint32_t *dev_vstar, void *stream);
 
+/* ----------------------------------------------------------------------------------------
+ * Calibration surrogate: a multilayer perceptron d_in -> H -> H -> d_out with SiLU hidden
+ * activations, trained and evaluated on the GPU by bfloat16 matrix-core kernels with fp32
+ * accumulation.  It is not part of the paper's method: it maps agent-population parameters to
+ * ensemble statistics for the parameter sweeps the paper motivates (section IV-J), with the
+ * exact engine above as its fallback and the judge of its error.
+ *
+ * Parameter layout (fp32, row-major, input index first), P = cae_mlp_sizes().n_params floats:
+ *   W1[d_in][H], b1[H], W2[H][H], b2[H], W3[H][d_out], b3[d_out]
+ * bfloat16 weight copies (n_weights halfwords): W1, W2, W3 in the same layouts, back to back.
+ * bfloat16 (round to nearest even) is stored for the inputs, weights, hidden activations and
+ * back-propagated gradients; products are accumulated in fp32; biases, pre-activations,
+ * outputs, weight gradients and Adam moments are fp32.
+ * Constraints: 1 <= d_in <= 64, H a multiple of 16 in 16..1024, 1 <= d_out <= 16.
+ * ------------------------------------------------------------------------------------- */
+typedef struct cae_mlp {
+    uint32_t d_in, d_hidden, d_out, flags; /* flags: 0                                       */
+    float *params;                         /* device, caller-owned fp32 parameters           */
+    uint16_t *weights;                     /* device, caller-owned bfloat16 weight copies    */
+} cae_mlp;
+
+typedef struct cae_mlp_sizes_t {
+    uint64_t n_params;        /* fp32 parameters                                            */
+    uint64_t n_weights;       /* bfloat16 weight copies                                     */
+    uint64_t workspace_bytes; /* per cae_mlp_forward/backward call with N <= max_batch      */
+} cae_mlp_sizes_t;
+
+/* Sizes for a network of the given shape and batches of at most max_batch samples.  Host only. */
+int cae_mlp_sizes(uint32_t d_in, uint32_t d_hidden, uint32_t d_out, uint32_t max_batch, cae_mlp_sizes_t *out);
+
+/* Rewrite the bfloat16 weight copies from net->params (after initialising or loading the
+ * parameters).  Asynchronous on stream. */
+int cae_mlp_refresh_weights(const cae_mlp *net, void *stream);
+
+/* y[N][d_out] (fp32, device) = network(x[N][d_in] (fp32, device)).  ws (device, workspace_bytes
+ * for a batch >= N) receives the activations that cae_mlp_backward reuses.  Asynchronous. */
+int cae_mlp_forward(const cae_mlp *net, const float *x, float *y, uint32_t N, void *ws, void *stream);
+
+/* Gradient of sum_{n,k} dy[n][k] * y[n][k] with respect to every parameter, summed over the N
+ * samples, written to grads (device, n_params fp32 in the parameter layout).  ws must hold the
+ * activations of the preceding cae_mlp_forward on the same N inputs (x itself is not read).
+ * N >= 1.  Asynchronous. */
+int cae_mlp_backward(const cae_mlp *net, const float *x, const float *dy, float *grads, uint32_t N, void *ws,
+                     void *stream);
+
+/* One Adam step (Kingma and Ba 2015, algorithm 1; step counts from 1) on net->params with the
+ * fp32 moments m, v (device, n_params each, zero before step 1); refreshes the bfloat16 weight
+ * copies.  Asynchronous. */
+int cae_mlp_adam(const cae_mlp *net, const float *grads, float *m, float *v, uint32_t step, float lr, float beta1,
+                 float beta2, float eps, void *stream);
+
+/* Mean squared error over n values: dy = 2 (y - target) / n and loss[0] = mean (y - target)^2
+ * (device pointers; one workgroup, fixed summation order).  Asynchronous. */
+int cae_mlp_mse_grad(const float *y, const float *target, float *dy, float *loss, uint32_t n, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -42,6 +42,16 @@ class Tuning(C.Structure):
                 ("class_cost", C.c_float * NUM_CLASSES)]
 
 
+class Mlp(C.Structure):
+    _fields_ = [("d_in", C.c_uint32), ("d_hidden", C.c_uint32), ("d_out", C.c_uint32),
+                ("flags", C.c_uint32), ("params", C.c_void_p), ("weights", C.c_void_p)]
+
+
+class MlpSizes(C.Structure):
+    _fields_ = [("n_params", C.c_uint64), ("n_weights", C.c_uint64),
+                ("workspace_bytes", C.c_uint64)]
+
+
 class CaeError(RuntimeError):
     def __init__(self, fn, code, msg):
         super().__init__("%s failed (%d): %s" % (fn, code, msg))
@@ -50,7 +60,9 @@ class CaeError(RuntimeError):
 
 EXPORTS = ["cae_strerror", "cae_last_error", "cae_device_info", "cae_sizes", "cae_create",
            "cae_step", "cae_read_books", "cae_read_state", "cae_write_state", "cae_get_tuning",
-           "cae_last_step_ms", "cae_destroy", "cae_clear"]
+           "cae_last_step_ms", "cae_destroy", "cae_clear", "cae_mlp_sizes",
+           "cae_mlp_refresh_weights", "cae_mlp_forward", "cae_mlp_backward", "cae_mlp_adam",
+           "cae_mlp_mse_grad"]
 
 _lib = None
 
@@ -78,6 +90,13 @@ def lib():
     L.cae_last_step_ms.argtypes = [P, P]
     L.cae_destroy.argtypes = [P]
     L.cae_clear.argtypes = [u32, u32, P, P, P, P]
+    f32 = C.c_float
+    L.cae_mlp_sizes.argtypes = [u32, u32, u32, u32, P]
+    L.cae_mlp_refresh_weights.argtypes = [P, P]
+    L.cae_mlp_forward.argtypes = [P, P, P, u32, P, P]
+    L.cae_mlp_backward.argtypes = [P, P, P, P, u32, P, P]
+    L.cae_mlp_adam.argtypes = [P, P, P, P, u32, f32, f32, f32, f32, P]
+    L.cae_mlp_mse_grad.argtypes = [P, P, P, P, u32, P]
     for name in EXPORTS:
         if name not in ("cae_strerror", "cae_last_error"):
             getattr(L, name).restype = i32

@@ -823,6 +823,10 @@ int build_schedule(cae_ensemble *e, const cae_tuning *tn, const uint32_t *ids,
 
 }  // namespace
 
+namespace cae_detail {
+int set_error(int code, const char *msg) { return fail(code, "%s", msg); }
+}  // namespace cae_detail
+
 extern "C" {
 
 const char *cae_strerror(int code)

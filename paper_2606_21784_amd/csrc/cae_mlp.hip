@@ -1,0 +1,407 @@
+// cae_mlp.hip -- bfloat16 matrix-core training and inference kernels of the calibration surrogate.
+//
+// The surrogate is a multilayer perceptron d_in -> H -> H -> d_out with SiLU hidden activations
+// that maps agent-population parameters to ensemble statistics.  It is not part of the paper's
+// method; it accelerates the parameter sweeps the paper motivates (section IV-J) and the exact
+// engine stays its fallback and its judge.
+//
+// Precision: weights, inputs, hidden activations and back-propagated gradients are stored in
+// bfloat16 (round to nearest even); every product is accumulated in fp32 by
+// v_mfma_f32_16x16x16bf16_1k; biases, pre-activations, outputs, weight gradients and the Adam
+// state are fp32.  Parameter layout (row-major, input index first):
+//   W1[d_in][H], b1[H], W2[H][H], b2[H], W3[H][d_out], b3[d_out]
+// and the bfloat16 weight copies are W1, W2, W3 in the same layouts, back to back.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+
+#include "cae.h"
+
+namespace {
+
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t f2bf(float f)  // round to nearest even
+{
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7F800000u) == 0x7F800000u) return (uint16_t)(u >> 16);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ float silu(float z) { return z / (1.0f + expf(-z)); }
+
+__device__ __forceinline__ float dsilu(float z)
+{
+    const float s = 1.0f / (1.0f + expf(-z));
+    return s * (1.0f + z * (1.0f - s));
+}
+
+enum Epi : int {
+    EPI_HIDDEN = 0,  // z = acc + bias -> Z (f32), H = bf16(silu(z))
+    EPI_OUTPUT = 1,  // y = acc + bias -> f32
+    EPI_DSILU = 2,   // dz = bf16(acc * silu'(Z))
+    EPI_F32 = 3,     // acc -> f32
+};
+
+struct GemmArgs {
+    const uint16_t *A;  // bf16, M x K (or K x M when transposed)
+    const uint16_t *B;  // bf16, K x N (or N x K when transposed)
+    uint32_t lda, ldb;
+    uint32_t M, N, K;
+    const float *bias;  // EPI_HIDDEN / EPI_OUTPUT
+    const float *Zin;   // EPI_DSILU: pre-activations (M x N, ld = ldo)
+    float *Of;          // f32 output (Z, y, or gradient), ld = ldo
+    uint16_t *Ob;       // bf16 output (H or dz), ld = ldo
+    uint32_t ldo;
+};
+
+// C = A * B with one wave per 16x16 output tile (four tiles per workgroup).  MFMA operand
+// layout (16x16x16): lane l holds A[l%16][4*(l/16)+t] and B[4*(l/16)+t][l%16], t = 0..3, and
+// receives C[4*(l/16)+t][l%16].
+template <bool TA, bool TB, int EPI>
+__global__ void __launch_bounds__(256) mlp_gemm(const GemmArgs g)
+{
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wave = threadIdx.x >> 6;
+    const uint32_t tiles_n = (g.N + 15u) / 16u;
+    const uint32_t tile = blockIdx.x * 4u + wave;
+    const uint32_t ti = tile / tiles_n, tj = tile % tiles_n;
+    if (ti * 16u >= g.M) return;
+    const uint32_t r = lane & 15u, grp = lane >> 4;
+    const uint32_t row = ti * 16u + r;  // A row this lane feeds
+    const uint32_t col = tj * 16u + r;  // B column this lane feeds
+    v4f acc = {0.f, 0.f, 0.f, 0.f};
+    for (uint32_t k0 = 0; k0 < g.K; k0 += 16u) {
+        v4s a, b;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const uint32_t k = k0 + 4u * grp + (uint32_t)t;
+            uint16_t av = 0, bv = 0;
+            if (row < g.M && k < g.K) av = TA ? g.A[(size_t)k * g.lda + row] : g.A[(size_t)row * g.lda + k];
+            if (col < g.N && k < g.K) bv = TB ? g.B[(size_t)col * g.ldb + k] : g.B[(size_t)k * g.ldb + col];
+            a[t] = (short)av;
+            b[t] = (short)bv;
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+    }
+    const uint32_t j = tj * 16u + r;
+    if (j >= g.N) return;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const uint32_t i = ti * 16u + 4u * grp + (uint32_t)t;
+        if (i >= g.M) continue;
+        const size_t o = (size_t)i * g.ldo + j;
+        if constexpr (EPI == EPI_HIDDEN) {
+            const float z = acc[t] + g.bias[j];
+            g.Of[o] = z;
+            g.Ob[o] = f2bf(silu(z));
+        } else if constexpr (EPI == EPI_OUTPUT) {
+            g.Of[o] = acc[t] + g.bias[j];
+        } else if constexpr (EPI == EPI_DSILU) {
+            g.Ob[o] = f2bf(acc[t] * dsilu(g.Zin[o]));
+        } else {
+            g.Of[o] = acc[t];
+        }
+    }
+}
+
+__global__ void to_bf16(const float *x, uint16_t *y, uint64_t n)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        y[i] = f2bf(x[i]);
+}
+
+// out[j] = sum over rows of bf16 matrix X[rows][cols] (fixed row order: deterministic)
+__global__ void colsum_bf16(const uint16_t *X, uint32_t rows, uint32_t cols, float *out)
+{
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= cols) return;
+    float s = 0.f;
+    for (uint32_t i = 0; i < rows; ++i) s += bf2f(X[(size_t)i * cols + j]);
+    out[j] = s;
+}
+
+// dy = 2 (y - t) / n, loss = mean (y - t)^2, one workgroup, fixed reduction order.
+__global__ void __launch_bounds__(1024) mse_grad(const float *y, const float *t, float *dy, float *loss, uint32_t n)
+{
+    __shared__ float part[1024];
+    float s = 0.f;
+    const float scale = 2.0f / (float)n;
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+        const float d = y[i] - t[i];
+        dy[i] = scale * d;
+        s += d * d;
+    }
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (uint32_t w = blockDim.x / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) loss[0] = part[0] / (float)n;
+}
+
+struct Layout {
+    uint64_t w1, b1, w2, b2, w3, b3, P;  // param offsets
+    uint64_t W;                          // bf16 weight count
+};
+
+__host__ __device__ inline Layout layout(uint32_t din, uint32_t H, uint32_t dout)
+{
+    Layout l;
+    l.w1 = 0;
+    l.b1 = l.w1 + (uint64_t)din * H;
+    l.w2 = l.b1 + H;
+    l.b2 = l.w2 + (uint64_t)H * H;
+    l.w3 = l.b2 + H;
+    l.b3 = l.w3 + (uint64_t)H * dout;
+    l.P = l.b3 + dout;
+    l.W = (uint64_t)din * H + (uint64_t)H * H + (uint64_t)H * dout;
+    return l;
+}
+
+// Adam (Kingma and Ba 2015, algorithm 1) on the fp32 parameters; weights also refresh their
+// bfloat16 copies.  c1 = 1 - beta1^t, c2 = 1 - beta2^t.
+__global__ void adam_step(float *p, const float *g, float *m, float *v, uint16_t *wb, Layout l, float lr,
+                          float beta1, float beta2, float eps, float c1, float c2, int update)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < l.P; i += (uint64_t)gridDim.x * blockDim.x) {
+        float pi = p[i];
+        if (update) {
+            const float gi = g[i];
+            const float mi = beta1 * m[i] + (1.0f - beta1) * gi;
+            const float vi = beta2 * v[i] + (1.0f - beta2) * gi * gi;
+            m[i] = mi;
+            v[i] = vi;
+            pi -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+            p[i] = pi;
+        }
+        int64_t w = -1;  // index in the bf16 copies
+        if (i < l.b1) w = (int64_t)i;
+        else if (i >= l.w2 && i < l.b2) w = (int64_t)(l.b1 + (i - l.w2));
+        else if (i >= l.w3 && i < l.b3) w = (int64_t)(l.b1 + (l.b2 - l.w2) + (i - l.w3));
+        if (w >= 0) wb[w] = f2bf(pi);
+    }
+}
+
+}  // namespace
+
+namespace cae_detail {
+int set_error(int code, const char *msg);  // cae_engine.hip: message for cae_last_error()
+}
+
+namespace {
+
+int mfail(int code, const char *msg) { return cae_detail::set_error(code, msg); }
+
+struct WsLayout {
+    size_t xb, z1, h1, z2, h2, dyb, dz2, dz1, total;
+};
+
+size_t al(size_t x) { return (x + 255) / 256 * 256; }
+
+WsLayout ws_layout(uint32_t din, uint32_t H, uint32_t dout, uint32_t N)
+{
+    WsLayout w;
+    size_t o = 0;
+    w.xb = o; o = al(o + 2ull * N * din);
+    w.z1 = o; o = al(o + 4ull * N * H);
+    w.h1 = o; o = al(o + 2ull * N * H);
+    w.z2 = o; o = al(o + 4ull * N * H);
+    w.h2 = o; o = al(o + 2ull * N * H);
+    w.dyb = o; o = al(o + 2ull * N * dout);
+    w.dz2 = o; o = al(o + 2ull * N * H);
+    w.dz1 = o; o = al(o + 2ull * N * H);
+    w.total = o;
+    return w;
+}
+
+int check_net(const cae_mlp *net)
+{
+    if (!net || !net->params || !net->weights) return mfail(CAE_EINVAL, "NULL network or buffer");
+    if (net->d_in < 1 || net->d_in > 64) return mfail(CAE_EINVAL, "d_in must be in 1..64");
+    if (net->d_hidden < 16 || net->d_hidden > 1024 || net->d_hidden % 16)
+        return mfail(CAE_EINVAL, "d_hidden must be a multiple of 16 in 16..1024");
+    if (net->d_out < 1 || net->d_out > 16) return mfail(CAE_EINVAL, "d_out must be in 1..16");
+    return CAE_OK;
+}
+
+template <bool TA, bool TB, int EPI>
+void gemm(const GemmArgs &g, hipStream_t s)
+{
+    const uint32_t tiles = ((g.M + 15u) / 16u) * ((g.N + 15u) / 16u);
+    hipLaunchKernelGGL((mlp_gemm<TA, TB, EPI>), dim3((tiles + 3u) / 4u), dim3(256), 0, s, g);
+}
+
+GemmArgs gargs(const uint16_t *A, uint32_t lda, const uint16_t *B, uint32_t ldb, uint32_t M, uint32_t N, uint32_t K)
+{
+    GemmArgs g{};
+    g.A = A;
+    g.B = B;
+    g.lda = lda;
+    g.ldb = ldb;
+    g.M = M;
+    g.N = N;
+    g.K = K;
+    return g;
+}
+
+int launch_status()
+{
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return mfail(CAE_EHIP, hipGetErrorString(e));
+    return CAE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cae_mlp_sizes(uint32_t d_in, uint32_t d_hidden, uint32_t d_out, uint32_t max_batch, cae_mlp_sizes_t *out)
+{
+    if (!out) return mfail(CAE_EINVAL, "out is NULL");
+    cae_mlp probe{d_in, d_hidden, d_out, 0, reinterpret_cast<float *>(1), reinterpret_cast<uint16_t *>(1)};
+    int rc = check_net(&probe);
+    if (rc) return rc;
+    const Layout l = layout(d_in, d_hidden, d_out);
+    out->n_params = l.P;
+    out->n_weights = l.W;
+    out->workspace_bytes = ws_layout(d_in, d_hidden, d_out, max_batch).total;
+    return CAE_OK;
+}
+
+int cae_mlp_refresh_weights(const cae_mlp *net, void *stream)
+{
+    int rc = check_net(net);
+    if (rc) return rc;
+    const Layout l = layout(net->d_in, net->d_hidden, net->d_out);
+    hipLaunchKernelGGL(adam_step, dim3(256), dim3(256), 0, (hipStream_t)stream, net->params, nullptr, nullptr,
+                       nullptr, net->weights, l, 0.f, 0.f, 0.f, 0.f, 1.f, 1.f, 0);
+    return launch_status();
+}
+
+int cae_mlp_forward(const cae_mlp *net, const float *x, float *y, uint32_t N, void *ws, void *stream)
+{
+    int rc = check_net(net);
+    if (rc) return rc;
+    if (!x || !y || !ws) return mfail(CAE_EINVAL, "NULL x, y or workspace");
+    if (N == 0) return CAE_OK;
+    hipStream_t s = (hipStream_t)stream;
+    const uint32_t din = net->d_in, H = net->d_hidden, dout = net->d_out;
+    const Layout l = layout(din, H, dout);
+    const WsLayout w = ws_layout(din, H, dout, N);
+    unsigned char *b = static_cast<unsigned char *>(ws);
+    uint16_t *xb = reinterpret_cast<uint16_t *>(b + w.xb);
+    float *z1 = reinterpret_cast<float *>(b + w.z1);
+    uint16_t *h1 = reinterpret_cast<uint16_t *>(b + w.h1);
+    float *z2 = reinterpret_cast<float *>(b + w.z2);
+    uint16_t *h2 = reinterpret_cast<uint16_t *>(b + w.h2);
+    const uint16_t *W1 = net->weights, *W2 = W1 + (size_t)din * H, *W3 = W2 + (size_t)H * H;
+    const uint64_t nx = (uint64_t)N * din;
+    hipLaunchKernelGGL(to_bf16, dim3((uint32_t)std::min<uint64_t>((nx + 255) / 256, 1024)), dim3(256), 0, s, x, xb, nx);
+    GemmArgs g = gargs(xb, din, W1, H, N, H, din);
+    g.bias = net->params + l.b1;
+    g.Of = z1;
+    g.Ob = h1;
+    g.ldo = H;
+    gemm<false, false, EPI_HIDDEN>(g, s);
+    g = gargs(h1, H, W2, H, N, H, H);
+    g.bias = net->params + l.b2;
+    g.Of = z2;
+    g.Ob = h2;
+    g.ldo = H;
+    gemm<false, false, EPI_HIDDEN>(g, s);
+    g = gargs(h2, H, W3, dout, N, dout, H);
+    g.bias = net->params + l.b3;
+    g.Of = y;
+    g.ldo = dout;
+    gemm<false, false, EPI_OUTPUT>(g, s);
+    return launch_status();
+}
+
+int cae_mlp_backward(const cae_mlp *net, const float *x, const float *dy, float *grads, uint32_t N, void *ws,
+                     void *stream)
+{
+    (void)x;  // the bfloat16 input is taken from the forward pass's workspace
+    int rc = check_net(net);
+    if (rc) return rc;
+    if (!dy || !grads || !ws) return mfail(CAE_EINVAL, "NULL dy, grads or workspace");
+    hipStream_t s = (hipStream_t)stream;
+    const uint32_t din = net->d_in, H = net->d_hidden, dout = net->d_out;
+    const Layout l = layout(din, H, dout);
+    const WsLayout w = ws_layout(din, H, dout, N);
+    unsigned char *b = static_cast<unsigned char *>(ws);
+    const uint16_t *xb = reinterpret_cast<const uint16_t *>(b + w.xb);
+    const float *z1 = reinterpret_cast<const float *>(b + w.z1);
+    const uint16_t *h1 = reinterpret_cast<const uint16_t *>(b + w.h1);
+    const float *z2 = reinterpret_cast<const float *>(b + w.z2);
+    const uint16_t *h2 = reinterpret_cast<const uint16_t *>(b + w.h2);
+    uint16_t *dyb = reinterpret_cast<uint16_t *>(b + w.dyb);
+    uint16_t *dz2 = reinterpret_cast<uint16_t *>(b + w.dz2);
+    uint16_t *dz1 = reinterpret_cast<uint16_t *>(b + w.dz1);
+    const uint16_t *W1 = net->weights, *W2 = W1 + (size_t)din * H, *W3 = W2 + (size_t)H * H;
+    (void)W1;
+    if (N == 0) return mfail(CAE_EINVAL, "backward needs N >= 1");
+    const uint64_t ny = (uint64_t)N * dout;
+    hipLaunchKernelGGL(to_bf16, dim3((uint32_t)std::min<uint64_t>((ny + 255) / 256, 1024)), dim3(256), 0, s, dy, dyb, ny);
+    // output layer: dW3 = h2^T dy, db3 = colsum(dy)
+    GemmArgs g = gargs(h2, H, dyb, dout, H, dout, N);
+    g.Of = grads + l.w3;
+    g.ldo = dout;
+    gemm<true, false, EPI_F32>(g, s);
+    hipLaunchKernelGGL(colsum_bf16, dim3(1), dim3(64), 0, s, dyb, N, dout, grads + l.b3);
+    // dz2 = (dy W3^T) * silu'(z2)
+    g = gargs(dyb, dout, W3, dout, N, H, dout);
+    g.Zin = z2;
+    g.Ob = dz2;
+    g.ldo = H;
+    gemm<false, true, EPI_DSILU>(g, s);
+    g = gargs(h1, H, dz2, H, H, H, N);
+    g.Of = grads + l.w2;
+    g.ldo = H;
+    gemm<true, false, EPI_F32>(g, s);
+    hipLaunchKernelGGL(colsum_bf16, dim3((H + 255) / 256), dim3(256), 0, s, dz2, N, H, grads + l.b2);
+    // dz1 = (dz2 W2^T) * silu'(z1)
+    g = gargs(dz2, H, W2, H, N, H, H);
+    g.Zin = z1;
+    g.Ob = dz1;
+    g.ldo = H;
+    gemm<false, true, EPI_DSILU>(g, s);
+    g = gargs(xb, din, dz1, H, din, H, N);
+    g.Of = grads + l.w1;
+    g.ldo = H;
+    gemm<true, false, EPI_F32>(g, s);
+    hipLaunchKernelGGL(colsum_bf16, dim3((H + 255) / 256), dim3(256), 0, s, dz1, N, H, grads + l.b1);
+    return launch_status();
+}
+
+int cae_mlp_adam(const cae_mlp *net, const float *grads, float *m, float *v, uint32_t step, float lr, float beta1,
+                 float beta2, float eps, void *stream)
+{
+    int rc = check_net(net);
+    if (rc) return rc;
+    if (!grads || !m || !v) return mfail(CAE_EINVAL, "NULL grads or moments");
+    if (step < 1) return mfail(CAE_EINVAL, "step counts from 1");
+    const Layout l = layout(net->d_in, net->d_hidden, net->d_out);
+    const float c1 = (float)(1.0 - std::pow((double)beta1, (double)step));
+    const float c2 = (float)(1.0 - std::pow((double)beta2, (double)step));
+    hipLaunchKernelGGL(adam_step, dim3((uint32_t)std::min<uint64_t>((l.P + 255) / 256, 1024)), dim3(256), 0,
+                       (hipStream_t)stream, net->params, grads, m, v, net->weights, l, lr, beta1, beta2, eps, c1, c2, 1);
+    return launch_status();
+}
+
+int cae_mlp_mse_grad(const float *y, const float *target, float *dy, float *loss, uint32_t n, void *stream)
+{
+    if (!y || !target || !dy || !loss) return mfail(CAE_EINVAL, "NULL pointer");
+    if (n == 0) return mfail(CAE_EINVAL, "n must be >= 1");
+    hipLaunchKernelGGL(mse_grad, dim3(1), dim3(1024), 0, (hipStream_t)stream, y, target, dy, loss, n);
+    return launch_status();
+}
+
+}  // extern "C"

@@ -1,0 +1,106 @@
+"""The calibration surrogate's network on the GPU: a d_in -> H -> H -> d_out SiLU perceptron
+with bfloat16 weights trained by libcae's matrix-core kernels (forward, backward, Adam).
+
+PyTorch only owns the device buffers and the stream; every step runs in libcae.
+"""
+import ctypes as C
+
+import numpy as np
+
+from ._lib import Mlp, MlpSizes, check, lib
+
+
+class MLP:
+    def __init__(self, d_in=4, d_hidden=256, d_out=3, max_batch=8192, seed=0, device=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("the surrogate network needs a ROCm GPU")
+        self.dims = (int(d_in), int(d_hidden), int(d_out))
+        self.max_batch = int(max_batch)
+        sz = MlpSizes()
+        check("cae_mlp_sizes", lib().cae_mlp_sizes(d_in, d_hidden, d_out, self.max_batch, C.byref(sz)))
+        self.n_params = int(sz.n_params)
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        dev = self.device
+        self.params = torch.zeros(self.n_params, dtype=torch.float32, device=dev)
+        self.weights = torch.zeros(int(sz.n_weights), dtype=torch.int16, device=dev)
+        self.grads = torch.zeros(self.n_params, dtype=torch.float32, device=dev)
+        self.m = torch.zeros(self.n_params, dtype=torch.float32, device=dev)
+        self.v = torch.zeros(self.n_params, dtype=torch.float32, device=dev)
+        self.ws = torch.empty(int(sz.workspace_bytes), dtype=torch.uint8, device=dev)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=dev)
+        self.net = Mlp(d_in, d_hidden, d_out, 0, self.params.data_ptr(), self.weights.data_ptr())
+        self.step_count = 0
+        self._last_n = None
+        self.set_params(self.init_params(seed))
+
+    @property
+    def stream(self):
+        import torch
+        return C.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+
+    def init_params(self, seed):
+        """Weights N(0, 1/fan_in), biases zero (host draw with a fixed seed)."""
+        d_in, H, d_out = self.dims
+        rng = np.random.Generator(np.random.PCG64(seed))
+        parts = [rng.normal(0, 1 / np.sqrt(d_in), d_in * H), np.zeros(H),
+                 rng.normal(0, 1 / np.sqrt(H), H * H), np.zeros(H),
+                 rng.normal(0, 1 / np.sqrt(H), H * d_out), np.zeros(d_out)]
+        return np.concatenate(parts).astype(np.float32)
+
+    def set_params(self, p):
+        import torch
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        assert p.size == self.n_params
+        self.params.copy_(torch.from_numpy(p))
+        check("cae_mlp_refresh_weights", lib().cae_mlp_refresh_weights(C.byref(self.net), self.stream))
+        self.m.zero_()
+        self.v.zero_()
+        self.step_count = 0
+
+    def get_params(self):
+        return self.params.detach().cpu().numpy().copy()
+
+    def forward(self, x, y=None):
+        """x: (N, d_in) float32 device tensor -> (N, d_out) float32 device tensor."""
+        import torch
+        n = int(x.shape[0])
+        if n > self.max_batch:
+            raise ValueError("batch %d exceeds max_batch %d" % (n, self.max_batch))
+        assert x.dtype == torch.float32 and x.is_contiguous() and x.shape[1] == self.dims[0]
+        if y is None:
+            y = torch.empty((n, self.dims[2]), dtype=torch.float32, device=self.device)
+        check("cae_mlp_forward", lib().cae_mlp_forward(C.byref(self.net), x.data_ptr(), y.data_ptr(),
+                                                       n, self.ws.data_ptr(), self.stream))
+        self._last_n = n
+        return y
+
+    def backward(self, x, dy):
+        """Gradients (fp32, parameter layout) of sum(dy * y) for the last forward's batch."""
+        n = int(dy.shape[0])
+        assert n == self._last_n, "backward must follow a forward on the same batch"
+        check("cae_mlp_backward", lib().cae_mlp_backward(C.byref(self.net), x.data_ptr(), dy.data_ptr(),
+                                                         self.grads.data_ptr(), n, self.ws.data_ptr(),
+                                                         self.stream))
+        return self.grads
+
+    def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        self.step_count += 1
+        check("cae_mlp_adam", lib().cae_mlp_adam(C.byref(self.net), self.grads.data_ptr(), self.m.data_ptr(),
+                                                 self.v.data_ptr(), self.step_count, lr, beta1, beta2, eps,
+                                                 self.stream))
+
+    def mse_grad(self, y, t, dy=None):
+        import torch
+        if dy is None:
+            dy = torch.empty_like(y)
+        check("cae_mlp_mse_grad", lib().cae_mlp_mse_grad(y.data_ptr(), t.data_ptr(), dy.data_ptr(),
+                                                         self.loss.data_ptr(), y.numel(), self.stream))
+        return dy
+
+    def train_step(self, x, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        y = self.forward(x)
+        dy = self.mse_grad(y, t)
+        self.backward(x, dy)
+        self.adam(lr, beta1, beta2, eps)
+        return self.loss

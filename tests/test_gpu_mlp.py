@@ -1,0 +1,118 @@
+"""Surrogate network kernels (bfloat16 matrix cores, fp32 accumulation) against the f64 oracle
+with bfloat16 rounding at the same points.  Through the C ABI."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mlp as OM
+
+pytestmark = pytest.mark.gpu
+
+
+def _mlp():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2606_21784_amd import mlp
+    oracle.lib()
+    return mlp
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-30))
+
+
+@pytest.mark.parametrize("dims,N", [((4, 256, 3), 300), ((7, 48, 5), 33), ((1, 16, 1), 1),
+                                    ((4, 256, 3), 4096)])
+def test_forward_matches_oracle(dims, N):
+    import torch
+    M = _mlp()
+    net = M.MLP(*dims, max_batch=max(N, 16), seed=1)
+    rng = np.random.default_rng(2)
+    p = net.get_params().astype(np.float64)
+    p[dims[0] * dims[1]:dims[0] * dims[1] + dims[1]] = rng.normal(0, 0.1, dims[1])  # nonzero b1
+    net.set_params(p)
+    x = rng.normal(0, 1, (N, dims[0])).astype(np.float32)
+    y = net.forward(torch.from_numpy(x).cuda()).cpu().numpy()
+    yo = OM.forward(net.get_params().astype(np.float64), dims, x.astype(np.float64), round_bf16=True)
+    assert _rel(y, yo) < 2e-3, _rel(y, yo)
+
+
+@pytest.mark.parametrize("dims,N", [((4, 256, 3), 256), ((7, 48, 5), 37)])
+def test_backward_matches_oracle(dims, N):
+    import torch
+    M = _mlp()
+    net = M.MLP(*dims, max_batch=N, seed=3)
+    rng = np.random.default_rng(4)
+    x = rng.normal(0, 1, (N, dims[0])).astype(np.float32)
+    dy = rng.normal(0, 1, (N, dims[2])).astype(np.float32)
+    xd = torch.from_numpy(x).cuda()
+    net.forward(xd)
+    g = net.backward(xd, torch.from_numpy(dy).cuda()).cpu().numpy().astype(np.float64)
+    go = OM.backward(net.get_params().astype(np.float64), dims, x.astype(np.float64),
+                     dy.astype(np.float64), round_bf16=True)
+    parts_g, parts_o = OM.split(g, dims), OM.split(go, dims)
+    for name, a, b in zip(["W1", "b1", "W2", "b2", "W3", "b3"], parts_g, parts_o):
+        assert _rel(a, b) < 5e-3, (name, _rel(a, b))
+    # and close to the exact (unrounded) gradient
+    ge = OM.backward(net.get_params().astype(np.float64), dims, x.astype(np.float64),
+                     dy.astype(np.float64), round_bf16=False)
+    assert np.linalg.norm(g - ge) / np.linalg.norm(ge) < 0.05
+
+
+def test_adam_matches_oracle():
+    import torch
+    M = _mlp()
+    dims = (4, 32, 3)
+    net = M.MLP(*dims, max_batch=64, seed=5)
+    rng = np.random.default_rng(6)
+    p = net.get_params().astype(np.float64)
+    m = np.zeros_like(p)
+    v = np.zeros_like(p)
+    for t in range(1, 6):
+        g = rng.normal(0, 1, p.size).astype(np.float32)
+        net.grads.copy_(torch.from_numpy(g))
+        net.adam(1e-3, 0.9, 0.999, 1e-8)
+        p, m, v = OM.adam(p, g.astype(np.float64), m, v, t, 1e-3, 0.9, 0.999, 1e-8)
+    np.testing.assert_allclose(net.get_params(), p, rtol=1e-5, atol=1e-6)
+    # bf16 weight copies follow the parameters
+    W = net.weights.cpu().numpy().view(np.uint16).astype(np.uint32) << 16
+    Wf = W.view(np.float32)
+    W1, b1, W2, b2, W3, b3 = OM.split(net.get_params(), dims)
+    ref = np.concatenate([W1.ravel(), W2.ravel(), W3.ravel()])
+    np.testing.assert_array_equal(Wf, OM.bf16(ref).astype(np.float32))
+
+
+def test_mse_grad():
+    import torch
+    M = _mlp()
+    net = M.MLP(4, 16, 3, max_batch=16, seed=0)
+    rng = np.random.default_rng(7)
+    y = rng.normal(0, 1, (1000, 3)).astype(np.float32)
+    t = rng.normal(0, 1, (1000, 3)).astype(np.float32)
+    dy = net.mse_grad(torch.from_numpy(y).cuda(), torch.from_numpy(t).cuda()).cpu().numpy()
+    np.testing.assert_allclose(dy, 2 * (y - t) / y.size, rtol=1e-6)
+    assert abs(float(net.loss.item()) - float(np.mean((y - t) ** 2))) < 1e-5
+
+
+def test_training_fits_smooth_function():
+    import torch
+    M = _mlp()
+    rng = np.random.default_rng(8)
+    x = rng.uniform(-1, 1, (4096, 4)).astype(np.float32)
+    t = np.stack([np.sin(2 * x[:, 0]) + x[:, 1] ** 2, x[:, 2] * x[:, 3], np.exp(0.5 * x[:, 0])],
+                 axis=1).astype(np.float32)
+    t = (t - t.mean(0)) / t.std(0)
+    net = M.MLP(4, 256, 3, max_batch=512, seed=9)
+    xd, td = torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda()
+    first = None
+    for epoch in range(60):
+        perm = torch.randperm(4096, device="cuda")
+        for b in range(8):
+            idx = perm[b * 512:(b + 1) * 512]
+            loss = net.train_step(xd[idx].contiguous(), td[idx].contiguous(), 2e-3)
+        if first is None:
+            first = float(loss.item())
+    y = net.forward(xd[:512].contiguous())
+    final = float(((y - td[:512]) ** 2).mean().item())
+    assert final < 0.02 and final < first / 10, (first, final)
