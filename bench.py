@@ -163,6 +163,8 @@ def main():
     ap.add_argument("--cpu-markets", type=int, default=1024)
     ap.add_argument("--no-uneven", action="store_true",
                     help="skip the uneven-ensemble leg (batched launch vs per-size launches)")
+    ap.add_argument("--no-surrogate", action="store_true",
+                    help="skip the calibration-surrogate leg (65536-draw sweep, training, judging)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="after timing, copy 1 GiB device-to-device (counter calibration)")
     args = ap.parse_args()
@@ -254,6 +256,12 @@ def main():
     ens.close()
     if not args.no_uneven:
         result["uneven"] = uneven_leg()
+    if not args.no_surrogate:
+        from paper_2606_21784_amd import surrogate
+        rep, _, _ = surrogate.run(log=log)
+        result["surrogate"] = rep
+        log("surrogate: speedup %.0f, mean rel err %s" %
+            (rep["speedup"], {k: round(v["mean"], 4) for k, v in rep["surrogate_rel_err"].items()}))
     print(json.dumps(result), flush=True)
 
 

@@ -238,9 +238,16 @@ int cae_mlp_backward(const cae_mlp *net, const float *x, const float *dy, float 
 int cae_mlp_adam(const cae_mlp *net, const float *grads, float *m, float *v, uint32_t step, float lr, float beta1,
                  float beta2, float eps, void *stream);
 
-/* Mean squared error over n values: dy = 2 (y - target) / n and loss[0] = mean (y - target)^2
- * (device pointers; one workgroup, fixed summation order).  Asynchronous. */
-int cae_mlp_mse_grad(const float *y, const float *target, float *dy, float *loss, uint32_t n, void *stream);
+/* Mean loss over n values and its gradient with respect to y, r = y - target (device pointers;
+ * one workgroup, fixed summation order).  Asynchronous.
+ *   CAE_LOSS_MSE:   loss[0] = mean r^2, dy = 2 r / n
+ *   CAE_LOSS_HUBER: loss[0] = mean of (r^2 / 2 if |r| <= delta else delta (|r| - delta / 2)),
+ *                   dy = clamp(r, -delta, delta) / n   (delta > 0)
+ * Errors: CAE_EINVAL (NULL, n == 0, unknown kind, delta <= 0 for Huber), CAE_EHIP. */
+#define CAE_LOSS_MSE 0
+#define CAE_LOSS_HUBER 1
+int cae_mlp_loss_grad(const float *y, const float *target, float *dy, float *loss, uint32_t n, int kind, float delta,
+                      void *stream);
 
 #ifdef __cplusplus
 }

@@ -62,7 +62,7 @@ EXPORTS = ["cae_strerror", "cae_last_error", "cae_device_info", "cae_sizes", "ca
            "cae_step", "cae_read_books", "cae_read_state", "cae_write_state", "cae_get_tuning",
            "cae_last_step_ms", "cae_destroy", "cae_clear", "cae_mlp_sizes",
            "cae_mlp_refresh_weights", "cae_mlp_forward", "cae_mlp_backward", "cae_mlp_adam",
-           "cae_mlp_mse_grad"]
+           "cae_mlp_loss_grad"]
 
 _lib = None
 
@@ -96,7 +96,7 @@ def lib():
     L.cae_mlp_forward.argtypes = [P, P, P, u32, P, P]
     L.cae_mlp_backward.argtypes = [P, P, P, P, u32, P, P]
     L.cae_mlp_adam.argtypes = [P, P, P, P, u32, f32, f32, f32, f32, P]
-    L.cae_mlp_mse_grad.argtypes = [P, P, P, P, u32, P]
+    L.cae_mlp_loss_grad.argtypes = [P, P, P, P, u32, i32, f32, P]
     for name in EXPORTS:
         if name not in ("cae_strerror", "cae_last_error"):
             getattr(L, name).restype = i32

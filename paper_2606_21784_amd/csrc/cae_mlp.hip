@@ -127,16 +127,27 @@ __global__ void colsum_bf16(const uint16_t *X, uint32_t rows, uint32_t cols, flo
     out[j] = s;
 }
 
-// dy = 2 (y - t) / n, loss = mean (y - t)^2, one workgroup, fixed reduction order.
-__global__ void __launch_bounds__(1024) mse_grad(const float *y, const float *t, float *dy, float *loss, uint32_t n)
+// Mean loss over n values and its gradient, one workgroup, fixed reduction order.
+//   kind 0 (squared error): loss = mean r^2,                         dy = 2 r / n
+//   kind 1 (Huber, delta):  loss = mean(r^2/2 if |r| <= delta else delta (|r| - delta/2)),
+//                           dy = clamp(r, -delta, delta) / n
+// with r = y - t.
+__global__ void __launch_bounds__(1024) loss_grad(const float *y, const float *t, float *dy, float *loss, uint32_t n,
+                                                  int kind, float delta)
 {
     __shared__ float part[1024];
     float s = 0.f;
-    const float scale = 2.0f / (float)n;
+    const float inv = 1.0f / (float)n;
     for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
         const float d = y[i] - t[i];
-        dy[i] = scale * d;
-        s += d * d;
+        if (kind == 0) {
+            dy[i] = 2.0f * d * inv;
+            s += d * d;
+        } else {
+            const float a = fabsf(d);
+            dy[i] = fminf(fmaxf(d, -delta), delta) * inv;
+            s += a <= delta ? 0.5f * d * d : delta * (a - 0.5f * delta);
+        }
     }
     part[threadIdx.x] = s;
     __syncthreads();
@@ -396,11 +407,14 @@ int cae_mlp_adam(const cae_mlp *net, const float *grads, float *m, float *v, uin
     return launch_status();
 }
 
-int cae_mlp_mse_grad(const float *y, const float *target, float *dy, float *loss, uint32_t n, void *stream)
+int cae_mlp_loss_grad(const float *y, const float *target, float *dy, float *loss, uint32_t n, int kind, float delta,
+                      void *stream)
 {
     if (!y || !target || !dy || !loss) return mfail(CAE_EINVAL, "NULL pointer");
     if (n == 0) return mfail(CAE_EINVAL, "n must be >= 1");
-    hipLaunchKernelGGL(mse_grad, dim3(1), dim3(1024), 0, (hipStream_t)stream, y, target, dy, loss, n);
+    if (kind != CAE_LOSS_MSE && kind != CAE_LOSS_HUBER) return mfail(CAE_EINVAL, "unknown loss kind");
+    if (kind == CAE_LOSS_HUBER && !(delta > 0.0f)) return mfail(CAE_EINVAL, "Huber delta must be > 0");
+    hipLaunchKernelGGL(loss_grad, dim3(1), dim3(1024), 0, (hipStream_t)stream, y, target, dy, loss, n, kind, delta);
     return launch_status();
 }
 

@@ -90,17 +90,20 @@ class MLP:
                                                  self.v.data_ptr(), self.step_count, lr, beta1, beta2, eps,
                                                  self.stream))
 
-    def mse_grad(self, y, t, dy=None):
+    def loss_grad(self, y, t, dy=None, huber_delta=None):
+        """Mean squared error (huber_delta None) or mean Huber loss and its gradient."""
         import torch
         if dy is None:
             dy = torch.empty_like(y)
-        check("cae_mlp_mse_grad", lib().cae_mlp_mse_grad(y.data_ptr(), t.data_ptr(), dy.data_ptr(),
-                                                         self.loss.data_ptr(), y.numel(), self.stream))
+        kind, delta = (0, 0.0) if huber_delta is None else (1, float(huber_delta))
+        check("cae_mlp_loss_grad", lib().cae_mlp_loss_grad(y.data_ptr(), t.data_ptr(), dy.data_ptr(),
+                                                           self.loss.data_ptr(), y.numel(), kind, delta,
+                                                           self.stream))
         return dy
 
-    def train_step(self, x, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    def train_step(self, x, t, lr, beta1=0.9, beta2=0.999, eps=1e-8, huber_delta=None):
         y = self.forward(x)
-        dy = self.mse_grad(y, t)
+        dy = self.loss_grad(y, t, huber_delta=huber_delta)
         self.backward(x, dy)
         self.adam(lr, beta1, beta2, eps)
         return self.loss

@@ -83,16 +83,25 @@ def test_adam_matches_oracle():
     np.testing.assert_array_equal(Wf, OM.bf16(ref).astype(np.float32))
 
 
-def test_mse_grad():
+@pytest.mark.parametrize("delta", [None, 0.05, 0.7])
+def test_loss_grad_matches_torch_autograd(delta):
     import torch
     M = _mlp()
     net = M.MLP(4, 16, 3, max_batch=16, seed=0)
     rng = np.random.default_rng(7)
     y = rng.normal(0, 1, (1000, 3)).astype(np.float32)
     t = rng.normal(0, 1, (1000, 3)).astype(np.float32)
-    dy = net.mse_grad(torch.from_numpy(y).cuda(), torch.from_numpy(t).cuda()).cpu().numpy()
-    np.testing.assert_allclose(dy, 2 * (y - t) / y.size, rtol=1e-6)
-    assert abs(float(net.loss.item()) - float(np.mean((y - t) ** 2))) < 1e-5
+    dy = net.loss_grad(torch.from_numpy(y).cuda(), torch.from_numpy(t).cuda(),
+                       huber_delta=delta).cpu().numpy()
+    yt = torch.tensor(y, dtype=torch.float64, requires_grad=True)
+    tt = torch.tensor(t, dtype=torch.float64)
+    if delta is None:
+        loss = torch.nn.functional.mse_loss(yt, tt)
+    else:
+        loss = torch.nn.functional.huber_loss(yt, tt, delta=delta)
+    loss.backward()
+    np.testing.assert_allclose(dy, yt.grad.numpy(), rtol=1e-5, atol=1e-9)
+    assert abs(float(net.loss.item()) - float(loss.item())) < 1e-5 * max(1.0, float(loss.item()))
 
 
 def test_training_fits_smooth_function():

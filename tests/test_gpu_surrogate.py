@@ -1,0 +1,45 @@
+"""Calibration surrogate end to end at a reduced size: the engine generates the sweep, the
+project's kernels train the network, the engine judges it.  The network must beat the
+predictors that use no network, and the engine's pooled statistics must equal the oracle's."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2606_21784_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _sur():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2606_21784_amd import surrogate
+    return surrogate
+
+
+def test_exact_statistics_match_oracle():
+    SG = _sur()
+    theta = W.calibration_params(40)[[3, 17, 29]]
+    ids = np.array([3, 17, 29])
+    Y = SG.exact_stats(theta, ids, seed=5, S=200, markets_per_draw=4)
+    for k in range(3):
+        d = W.calibration_markets(theta[k:k + 1], markets_per_draw=4)
+        mids = ids[k] * 4 + np.arange(4)
+        st, _ = oracle.run(d, 5, 200, ids=mids)
+        ref = oracle.pooled_stats(st, 200)
+        np.testing.assert_allclose(Y[k], ref, rtol=1e-9)
+
+
+def test_surrogate_beats_networkless_predictors():
+    SG = _sur()
+    data = SG.generate(n_draws=2048, markets_per_draw=16, S=400)
+    rep, net, scaler = SG.fit_and_evaluate(data, epochs=120, noise_draws=64)
+    s, lin, mean = (rep[k] for k in ("surrogate_rel_err", "linear_predictor_rel_err",
+                                     "mean_predictor_rel_err"))
+    for name in ("logret_variance", "mean_volume"):
+        assert s[name]["mean"] < 0.5 * lin[name]["mean"], (name, s[name], lin[name])
+        assert s[name]["mean"] < 0.5 * mean[name]["mean"], (name, s[name], mean[name])
+    assert rep["speedup"] > 10
+    demo = SG.calibration_demo(net, scaler, data, n_targets=2, n_candidates=2048, verify=2)
+    assert np.isfinite(demo["surrogate_dist_mean"]) and np.isfinite(demo["exact_only_dist_mean"])
