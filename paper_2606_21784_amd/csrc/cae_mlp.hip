@@ -54,6 +54,8 @@ struct GemmArgs {
     const uint16_t *B;  // bf16, K x N (or N x K when transposed)
     uint32_t lda, ldb;
     uint32_t M, N, K;
+    uint32_t ones_row;  // A has one extra row M of ones (its output row is the column sum of B)
+    uint32_t kchunk;    // K range per blockIdx.y (split K); partial sums go to Of + y * (M+1) * ldo
     const float *bias;  // EPI_HIDDEN / EPI_OUTPUT
     const float *Zin;   // EPI_DSILU: pre-activations (M x N, ld = ldo)
     float *Of;          // f32 output (Z, y, or gradient), ld = ldo
@@ -69,22 +71,28 @@ __global__ void __launch_bounds__(256) mlp_gemm(const GemmArgs g)
 {
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wave = threadIdx.x >> 6;
+    const uint32_t Mr = g.M + g.ones_row;  // rows of the output
     const uint32_t tiles_n = (g.N + 15u) / 16u;
     const uint32_t tile = blockIdx.x * 4u + wave;
     const uint32_t ti = tile / tiles_n, tj = tile % tiles_n;
-    if (ti * 16u >= g.M) return;
+    if (ti * 16u >= Mr) return;
     const uint32_t r = lane & 15u, grp = lane >> 4;
     const uint32_t row = ti * 16u + r;  // A row this lane feeds
     const uint32_t col = tj * 16u + r;  // B column this lane feeds
+    const uint32_t kbeg = blockIdx.y * g.kchunk;
+    const uint32_t kend = min(g.K, kbeg + g.kchunk);
     v4f acc = {0.f, 0.f, 0.f, 0.f};
-    for (uint32_t k0 = 0; k0 < g.K; k0 += 16u) {
+    for (uint32_t k0 = kbeg; k0 < kend; k0 += 16u) {
         v4s a, b;
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
             const uint32_t k = k0 + 4u * grp + (uint32_t)t;
             uint16_t av = 0, bv = 0;
-            if (row < g.M && k < g.K) av = TA ? g.A[(size_t)k * g.lda + row] : g.A[(size_t)row * g.lda + k];
-            if (col < g.N && k < g.K) bv = TB ? g.B[(size_t)col * g.ldb + k] : g.B[(size_t)k * g.ldb + col];
+            if (k < kend) {
+                if (row < g.M) av = TA ? g.A[(size_t)k * g.lda + row] : g.A[(size_t)row * g.lda + k];
+                else if (row == g.M && g.ones_row) av = 0x3F80u;  // bfloat16 1.0
+                if (col < g.N) bv = TB ? g.B[(size_t)col * g.ldb + k] : g.B[(size_t)k * g.ldb + col];
+            }
             a[t] = (short)av;
             b[t] = (short)bv;
         }
@@ -92,10 +100,11 @@ __global__ void __launch_bounds__(256) mlp_gemm(const GemmArgs g)
     }
     const uint32_t j = tj * 16u + r;
     if (j >= g.N) return;
+    float *Of = g.Of + (size_t)blockIdx.y * Mr * g.ldo;  // split-K partial (y = 0 when not split)
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
         const uint32_t i = ti * 16u + 4u * grp + (uint32_t)t;
-        if (i >= g.M) continue;
+        if (i >= Mr) continue;
         const size_t o = (size_t)i * g.ldo + j;
         if constexpr (EPI == EPI_HIDDEN) {
             const float z = acc[t] + g.bias[j];
@@ -106,8 +115,18 @@ __global__ void __launch_bounds__(256) mlp_gemm(const GemmArgs g)
         } else if constexpr (EPI == EPI_DSILU) {
             g.Ob[o] = f2bf(acc[t] * dsilu(g.Zin[o]));
         } else {
-            g.Of[o] = acc[t];
+            Of[o] = acc[t];
         }
+    }
+}
+
+// out[i] = sum over the `parts` split-K partial results, in partial order (deterministic).
+__global__ void sum_partials(const float *part, uint32_t parts, uint64_t n, float *out)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        float s = 0.f;
+        for (uint32_t p = 0; p < parts; ++p) s += part[(size_t)p * n + i];
+        out[i] = s;
     }
 }
 
@@ -115,16 +134,6 @@ __global__ void to_bf16(const float *x, uint16_t *y, uint64_t n)
 {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
         y[i] = f2bf(x[i]);
-}
-
-// out[j] = sum over rows of bf16 matrix X[rows][cols] (fixed row order: deterministic)
-__global__ void colsum_bf16(const uint16_t *X, uint32_t rows, uint32_t cols, float *out)
-{
-    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= cols) return;
-    float s = 0.f;
-    for (uint32_t i = 0; i < rows; ++i) s += bf2f(X[(size_t)i * cols + j]);
-    out[j] = s;
 }
 
 // Mean loss over n values and its gradient, one workgroup, fixed reduction order.
@@ -212,8 +221,11 @@ namespace {
 int mfail(int code, const char *msg) { return cae_detail::set_error(code, msg); }
 
 struct WsLayout {
-    size_t xb, z1, h1, z2, h2, dyb, dz2, dz1, total;
+    size_t xb, z1, h1, z2, h2, dyb, dz2, dz1, part, total;
 };
+
+constexpr uint32_t kSplitChunk = 256;  // batch rows per split-K part of a weight gradient
+constexpr uint32_t kMaxParts = 64;
 
 size_t al(size_t x) { return (x + 255) / 256 * 256; }
 
@@ -229,6 +241,9 @@ WsLayout ws_layout(uint32_t din, uint32_t H, uint32_t dout, uint32_t N)
     w.dyb = o; o = al(o + 2ull * N * dout);
     w.dz2 = o; o = al(o + 2ull * N * H);
     w.dz1 = o; o = al(o + 2ull * N * H);
+    const uint64_t parts = std::min<uint64_t>(kMaxParts, (N + kSplitChunk - 1) / kSplitChunk);
+    const uint64_t rows = std::max<uint64_t>(din, H) + 1;
+    w.part = o; o = al(o + 4ull * parts * rows * std::max<uint32_t>(H, dout));
     w.total = o;
     return w;
 }
@@ -244,10 +259,39 @@ int check_net(const cae_mlp *net)
 }
 
 template <bool TA, bool TB, int EPI>
-void gemm(const GemmArgs &g, hipStream_t s)
+void gemm(GemmArgs g, hipStream_t s)
 {
-    const uint32_t tiles = ((g.M + 15u) / 16u) * ((g.N + 15u) / 16u);
+    if (g.kchunk == 0) g.kchunk = g.K;
+    const uint32_t tiles = ((g.M + g.ones_row + 15u) / 16u) * ((g.N + 15u) / 16u);
     hipLaunchKernelGGL((mlp_gemm<TA, TB, EPI>), dim3((tiles + 3u) / 4u), dim3(256), 0, s, g);
+}
+
+// Weight gradient [M+1][N] = [A^T ; 1^T] B over the batch (the last row is the bias gradient),
+// split over batch chunks into partials and summed in chunk order.
+void weight_grad(const uint16_t *A, uint32_t lda, const uint16_t *B, uint32_t ldb, uint32_t M, uint32_t N,
+                 uint32_t batch, float *out, float *part, hipStream_t s)
+{
+    GemmArgs g{};
+    g.A = A;
+    g.B = B;
+    g.lda = lda;
+    g.ldb = ldb;
+    g.M = M;
+    g.N = N;
+    g.K = batch;
+    g.ones_row = 1;
+    g.ldo = N;
+    const uint32_t parts = std::min<uint32_t>(kMaxParts, (batch + kSplitChunk - 1) / kSplitChunk);
+    g.kchunk = ((batch + parts - 1) / parts + 15u) / 16u * 16u;
+    const uint32_t nparts = (batch + g.kchunk - 1) / g.kchunk;
+    g.Of = nparts > 1 ? part : out;
+    const uint32_t tiles = ((M + 1 + 15u) / 16u) * ((N + 15u) / 16u);
+    hipLaunchKernelGGL((mlp_gemm<true, false, EPI_F32>), dim3((tiles + 3u) / 4u, nparts), dim3(256), 0, s, g);
+    if (nparts > 1) {
+        const uint64_t n = (uint64_t)(M + 1) * N;
+        hipLaunchKernelGGL(sum_partials, dim3((uint32_t)std::min<uint64_t>((n + 255) / 256, 1024)), dim3(256), 0, s,
+                           part, nparts, n, out);
+    }
 }
 
 GemmArgs gargs(const uint16_t *A, uint32_t lda, const uint16_t *B, uint32_t ldb, uint32_t M, uint32_t N, uint32_t K)
@@ -356,39 +400,28 @@ int cae_mlp_backward(const cae_mlp *net, const float *x, const float *dy, float 
     uint16_t *dyb = reinterpret_cast<uint16_t *>(b + w.dyb);
     uint16_t *dz2 = reinterpret_cast<uint16_t *>(b + w.dz2);
     uint16_t *dz1 = reinterpret_cast<uint16_t *>(b + w.dz1);
+    float *part = reinterpret_cast<float *>(b + w.part);
     const uint16_t *W1 = net->weights, *W2 = W1 + (size_t)din * H, *W3 = W2 + (size_t)H * H;
     (void)W1;
     if (N == 0) return mfail(CAE_EINVAL, "backward needs N >= 1");
     const uint64_t ny = (uint64_t)N * dout;
     hipLaunchKernelGGL(to_bf16, dim3((uint32_t)std::min<uint64_t>((ny + 255) / 256, 1024)), dim3(256), 0, s, dy, dyb, ny);
-    // output layer: dW3 = h2^T dy, db3 = colsum(dy)
-    GemmArgs g = gargs(h2, H, dyb, dout, H, dout, N);
-    g.Of = grads + l.w3;
-    g.ldo = dout;
-    gemm<true, false, EPI_F32>(g, s);
-    hipLaunchKernelGGL(colsum_bf16, dim3(1), dim3(64), 0, s, dyb, N, dout, grads + l.b3);
+    // output layer: [dW3; db3] = [h2; 1]^T dy (b3 directly follows W3 in the layout)
+    weight_grad(h2, H, dyb, dout, H, dout, N, grads + l.w3, part, s);
     // dz2 = (dy W3^T) * silu'(z2)
-    g = gargs(dyb, dout, W3, dout, N, H, dout);
+    GemmArgs g = gargs(dyb, dout, W3, dout, N, H, dout);
     g.Zin = z2;
     g.Ob = dz2;
     g.ldo = H;
     gemm<false, true, EPI_DSILU>(g, s);
-    g = gargs(h1, H, dz2, H, H, H, N);
-    g.Of = grads + l.w2;
-    g.ldo = H;
-    gemm<true, false, EPI_F32>(g, s);
-    hipLaunchKernelGGL(colsum_bf16, dim3((H + 255) / 256), dim3(256), 0, s, dz2, N, H, grads + l.b2);
+    weight_grad(h1, H, dz2, H, H, H, N, grads + l.w2, part, s);
     // dz1 = (dz2 W2^T) * silu'(z1)
     g = gargs(dz2, H, W2, H, N, H, H);
     g.Zin = z1;
     g.Ob = dz1;
     g.ldo = H;
     gemm<false, true, EPI_DSILU>(g, s);
-    g = gargs(xb, din, dz1, H, din, H, N);
-    g.Of = grads + l.w1;
-    g.ldo = H;
-    gemm<true, false, EPI_F32>(g, s);
-    hipLaunchKernelGGL(colsum_bf16, dim3((H + 255) / 256), dim3(256), 0, s, dz1, N, H, grads + l.b1);
+    weight_grad(xb, din, dz1, H, din, H, N, grads + l.w1, part, s);
     return launch_status();
 }
 
