@@ -113,6 +113,12 @@ typedef struct cae_tuning {
     uint32_t max_lds_bytes;                     /* LDS budget per workgroup               */
     uint32_t flags;                             /* bit 0: keep descriptor order (no LPT)  */
     uint8_t waves_per_market[CAE_NUM_CLASSES];  /* 1,2,4,8,16 per size class; 0 = auto    */
+    uint8_t pipelined[CAE_NUM_CLASSES];         /* 1: markets of this class run in pairs
+                                                   that share all waves_per_group waves in
+                                                   alternating phases (one wave clears one
+                                                   market while the others generate the
+                                                   other's orders); waves_per_market is then
+                                                   ignored.  Needs waves_per_group >= 2.   */
     float class_cost[CAE_NUM_CLASSES];          /* relative cost of one market-step per
                                                    class for the longest-first order;
                                                    0 = the built-in model A + 2*64*TPL    */

@@ -39,6 +39,7 @@ class Tuning(C.Structure):
     _fields_ = [("waves_per_group", C.c_uint32), ("groups_per_cu", C.c_uint32),
                 ("max_lds_bytes", C.c_uint32), ("flags", C.c_uint32),
                 ("waves_per_market", C.c_uint8 * NUM_CLASSES),
+                ("pipelined", C.c_uint8 * NUM_CLASSES),
                 ("class_cost", C.c_float * NUM_CLASSES)]
 
 

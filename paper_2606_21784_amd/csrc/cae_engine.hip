@@ -53,9 +53,12 @@ static_assert(sizeof(DevMarket) == 48, "DevMarket layout");
 struct Item {
     uint32_t first;     // index into the market order list
     uint32_t count;     // markets in this item
-    uint32_t wpm_log2;  // log2(waves per market)
-    uint32_t stride;    // LDS words per market slice (book pairs + 8 scratch words)
+    uint32_t wpm_log2;  // log2(waves per market) (single-wave or lock-step items)
+    uint32_t stride;    // LDS words per market slice (book pairs + kScr scratch words)
+    uint32_t pipe;      // 1: two markets share all the workgroup's waves in alternating phases
 };
+
+constexpr uint32_t kScr = 32;  // scratch words at the end of every market slice
 
 struct EngineArgs {
     const DevMarket *desc;
@@ -160,6 +163,23 @@ __device__ __forceinline__ uint32_t wave_scan_add(uint32_t x)  // inclusive
     return x;
 }
 
+// Two inclusive scans interleaved, so each DPP read follows an unrelated write (no wait states).
+__device__ __forceinline__ void wave_scan_add2(uint32_t &x, uint32_t &y)
+{
+    x += dpp<0x111, 0xf>(x);
+    y += dpp<0x111, 0xf>(y);
+    x += dpp<0x112, 0xf>(x);
+    y += dpp<0x112, 0xf>(y);
+    x += dpp<0x114, 0xf>(x);
+    y += dpp<0x114, 0xf>(y);
+    x += dpp<0x118, 0xf>(x);
+    y += dpp<0x118, 0xf>(y);
+    x += dpp<0x142, 0xa>(x);
+    y += dpp<0x142, 0xa>(y);
+    x += dpp<0x143, 0xc>(x);
+    y += dpp<0x143, 0xc>(y);
+}
+
 __device__ __forceinline__ uint32_t wave_max(uint32_t x)  // uniform result
 {
     x = max(x, dpp<0x111, 0xf>(x));
@@ -244,8 +264,8 @@ __device__ __forceinline__ ClearOut clear_wave(uint32_t *__restrict__ bk, uint32
             sa += k[j];
         }
     }
-    const uint32_t ib = wave_scan_add(sb);
-    const uint32_t ia = wave_scan_add(sa);
+    uint32_t ib = sb, ia = sa;
+    wave_scan_add2(ib, ia);
     const uint32_t Tb = readlane(ib, 63);  // all bids
     const uint32_t eb = ib - sb;          // bids on ticks below this lane's first tick
     const uint32_t ea = ia - sa;          // asks on ticks below this lane's first tick
@@ -380,7 +400,7 @@ __device__ __forceinline__ void run_market(const EngineArgs &args, const Item &i
     const uint32_t nthr = 64u << item.wpm_log2;
     const uint32_t t = (w_in << 6) | lane;
     uint32_t *bk = lds + sub * item.stride;
-    uint32_t *scr = bk + item.stride - 8u;
+    uint32_t *scr = bk + item.stride - kScr;
 
     uint32_t m = 0;
     DevMarket d{};
@@ -477,6 +497,141 @@ __device__ __forceinline__ void run_market(const EngineArgs &args, const Item &i
     }
 }
 
+// Scratch layout of a pipelined market (32-bit words): 0 last, 1 prev, 2-3 steps at item start,
+// 4-5 n_trade, 6-7 sum_vol, 8-9 sum_px, 10-11 sum_spread, 12-13 n_spread, 14-15 sum_r,
+// 16-17 sum_r2.
+__device__ __forceinline__ uint64_t lds_u64(const uint32_t *p)
+{
+    const uint2 v = *reinterpret_cast<const uint2 *>(p);
+    return ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)v.y) << 32) |
+           (uint32_t)__builtin_amdgcn_readfirstlane((int)v.x);
+}
+
+__device__ __forceinline__ uint32_t lds_u32(const uint32_t *p)
+{
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)*p);
+}
+
+__device__ __forceinline__ void st_u64(uint32_t *p, uint64_t v)
+{
+    *reinterpret_cast<uint2 *>(p) = make_uint2((uint32_t)v, (uint32_t)(v >> 32));
+}
+
+// Two markets (A, B) share all G waves of the workgroup in alternating phases: in phase p one
+// wave (rotating) clears the market whose orders were aggregated in phase p-1 while the other
+// G-1 waves generate and aggregate the other market's orders.  One barrier per phase; no wave
+// waits for a clearing.  With one market the phases alternate between its orders and its
+// clearing.  Phase count: 2S (+1 to clear B's last step).
+template <int TPL_MAX>
+__device__ __forceinline__ void run_pair(const EngineArgs &args, const Item &item, uint32_t wave, uint32_t lane,
+                                         uint32_t G, uint32_t *lds)
+{
+    const uint32_t npair = item.count;
+    const uint32_t tid = (wave << 6) | lane;
+    const uint32_t nthr = G << 6;
+    DevMarket dA{}, dB{};  // two named descriptors: a runtime index into an array would spill
+    uint32_t mA = 0, mB = 0;
+#pragma unroll
+    for (uint32_t x = 0; x < 2; ++x) {
+        if (x < npair) {
+            const uint32_t m = args.order[item.first + x];
+            const DevMarket dm = args.desc[m];
+            if (x == 0) {
+                dA = dm;
+                mA = m;
+            } else {
+                dB = dm;
+                mB = m;
+            }
+            uint32_t *bk = lds + x * item.stride;
+            uint32_t *scr = bk + item.stride - kScr;
+            const uint32_t *gb = args.book + dm.book_off;
+            const uint32_t padded = 64u * dm.tpl;
+            for (uint32_t q = tid; q < padded; q += nthr) {
+                uint2 v = make_uint2(0u, 0u);
+                if (q < dm.L) {
+                    v.x = gb[q];
+                    v.y = gb[dm.L + q];
+                }
+                reinterpret_cast<uint2 *>(bk)[q] = v;
+            }
+            if (tid < 18u) scr[tid] = reinterpret_cast<const uint32_t *>(args.state + m)[tid];
+        }
+    }
+    __syncthreads();
+    const uint32_t S = args.S;
+    const uint32_t nph = 2u * S + (npair == 2u ? 1u : 0u);
+    uint32_t c = 0;  // clearing wave of this phase: p mod G
+    for (uint32_t p = 0; p < nph; ++p) {
+        const uint32_t X = p & 1u, Y = X ^ 1u;
+        if (wave == c) {
+            if (p >= 1u && Y < npair) {
+                uint32_t *bk = lds + Y * item.stride;
+                uint32_t *scr = bk + item.stride - kScr;
+                const DevMarket &dy = Y ? dB : dA;
+                const ClearOut co = clear_dispatch<TPL_MAX>(bk, dy.tpl, lane);
+                const uint32_t last0 = lds_u32(scr);
+                uint64_t n_trade = lds_u64(scr + 4), sum_vol = lds_u64(scr + 6), sum_px = lds_u64(scr + 8);
+                uint64_t sum_spread = lds_u64(scr + 10), n_spread = lds_u64(scr + 12);
+                const double sum_r = __longlong_as_double((long long)lds_u64(scr + 14));
+                const double sum_r2 = __longlong_as_double((long long)lds_u64(scr + 16));
+                uint32_t last = last0;
+                if (co.v != 0) {
+                    last = co.p;
+                    n_trade += 1;
+                    sum_vol += co.v;
+                    sum_px += co.p;
+                }
+                if (co.bb != kNone && co.ba != kNone) {
+                    sum_spread += (uint64_t)(co.ba - co.bb);
+                    n_spread += 1;
+                }
+                const double *lnT = args.lnT + dy.L;
+                const double r = lnT[last] - lnT[last0];
+                if (lane == 0) {
+                    scr[0] = last;
+                    scr[1] = last0;
+                    st_u64(scr + 4, n_trade);
+                    st_u64(scr + 6, sum_vol);
+                    st_u64(scr + 8, sum_px);
+                    st_u64(scr + 10, sum_spread);
+                    st_u64(scr + 12, n_spread);
+                    st_u64(scr + 14, (uint64_t)__double_as_longlong(sum_r + r));
+                    st_u64(scr + 16, (uint64_t)__double_as_longlong(sum_r2 + r * r));
+                }
+            }
+        } else if (p < 2u * S && X < npair) {
+            uint32_t *bk = lds + X * item.stride;
+            const uint32_t *scr = bk + item.stride - kScr;
+            const uint32_t last = lds_u32(scr), prev = lds_u32(scr + 1);
+            const uint32_t s = (uint32_t)lds_u64(scr + 2) + (p >> 1);
+            const uint32_t gidx = (wave + G - c - 1u) % G;  // 0 .. G-2
+            const DevMarket &dx = X ? dB : dA;
+            gen_orders(dx, dx.id, s, last, prev, args.k0, args.k1, (gidx << 6) | lane, (G - 1u) << 6, bk);
+        }
+        __syncthreads();
+        c = (c + 1u == G) ? 0u : c + 1u;
+    }
+#pragma unroll
+    for (uint32_t x = 0; x < 2; ++x) {
+        if (x < npair) {
+            const DevMarket &dm = x ? dB : dA;
+            const uint32_t m = x ? mB : mA;
+            const uint32_t *bk = lds + x * item.stride;
+            uint32_t *scr = lds + x * item.stride + item.stride - kScr;
+            uint32_t *gb = args.book + dm.book_off;
+            for (uint32_t q = tid; q < dm.L; q += nthr) {
+                const uint2 v = reinterpret_cast<const uint2 *>(bk)[q];
+                gb[q] = v.x;
+                gb[dm.L + q] = v.y;
+            }
+            if (tid == 0) st_u64(scr + 2, lds_u64(scr + 2) + S);
+            __syncthreads();
+            if (tid < 18u) reinterpret_cast<uint32_t *>(args.state + m)[tid] = scr[tid];
+        }
+    }
+}
+
 template <int TPL_MAX>
 __global__ void __launch_bounds__(1024) cae_engine_kernel(const EngineArgs args)
 {
@@ -497,7 +652,9 @@ __global__ void __launch_bounds__(1024) cae_engine_kernel(const EngineArgs args)
         const uint32_t sub = wave >> item.wpm_log2;
         const uint32_t w_in = wave & ((1u << item.wpm_log2) - 1u);
         const bool active = sub < item.count;
-        if (item.wpm_log2 == 0) {
+        if (item.pipe) {
+            run_pair<TPL_MAX>(args, item, wave, lane, blockDim.x >> 6, lds);
+        } else if (item.wpm_log2 == 0) {
             if (active) run_market<TPL_MAX, false>(args, item, sub, w_in, lane, true, lds);
         } else {
             run_market<TPL_MAX, true>(args, item, sub, w_in, lane, active, lds);
@@ -710,6 +867,8 @@ int build_schedule(cae_ensemble *e, const cae_tuning *tn, const uint32_t *ids,
         uint32_t w = t.waves_per_market[c];
         if (w == 0) w = auto_wpm(d.L, d.A);
         if (w > 16 || (w & (w - 1)) != 0) return fail(CAE_EINVAL, "waves_per_market[%u]=%u not a power of 2 <= 16", c, w);
+        if (t.pipelined[c] > 1) return fail(CAE_EINVAL, "pipelined[%u] must be 0 or 1", c);
+        if (t.pipelined[c]) w = 1;  // a pipelined pair uses the whole workgroup
         wpm[m] = w;
         t.waves_per_market[c] = (uint8_t)w;
         wpm_max = std::max(wpm_max, w);
@@ -718,6 +877,9 @@ int build_schedule(cae_ensemble *e, const cae_tuning *tn, const uint32_t *ids,
     uint32_t G = t.waves_per_group;
     if (G == 0) G = std::max(wpm_max, 4u);
     if (G > 16 || G < wpm_max) return fail(CAE_EINVAL, "waves_per_group=%u must be in [max waves_per_market=%u, 16]", G, wpm_max);
+    bool any_pipe = false;
+    for (uint32_t c = 0; c < CAE_NUM_CLASSES; ++c) any_pipe |= t.pipelined[c] != 0;
+    if (any_pipe && G < 2) return fail(CAE_EINVAL, "pipelined classes need waves_per_group >= 2");
     uint32_t lds_budget = t.max_lds_bytes ? t.max_lds_bytes : 64u * 1024u;
     if (lds_budget > 160u * 1024u) lds_budget = 160u * 1024u;
 
@@ -737,21 +899,22 @@ int build_schedule(cae_ensemble *e, const cae_tuning *tn, const uint32_t *ids,
     if (!keep)
         std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return cost[a] > cost[b]; });
 
-    // open bins per (wpm, tpl)
-    struct Bin { std::vector<uint32_t> ms; uint32_t wpm, tpl; };
+    // open bins per (wpm, tpl, pipelined)
+    struct Bin { std::vector<uint32_t> ms; uint32_t wpm, tpl, pipe; };
     std::vector<Bin> open;
     std::vector<std::pair<double, Bin>> done;
     for (uint32_t idx = 0; idx < M; ++idx) {
         const uint32_t m = order[idx];
         const uint32_t w = wpm[m], tp = tpl_for(e->desc[m].L);
-        const uint32_t stride = 2u * 64u * tp + 8u;
-        uint32_t cap = G / w;
+        const uint32_t pp = t.pipelined[lclass(e->desc[m].L) * 8u + aclass(e->desc[m].A)] ? 1u : 0u;
+        const uint32_t stride = 2u * 64u * tp + kScr;
+        uint32_t cap = pp ? 2u : G / w;
         cap = std::max(1u, std::min(cap, lds_budget / (stride * 4u)));
         Bin *b = nullptr;
         for (auto &x : open)
-            if (x.wpm == w && x.tpl == tp) b = &x;
+            if (x.wpm == w && x.tpl == tp && x.pipe == pp) b = &x;
         if (!b) {
-            open.push_back(Bin{{}, w, tp});
+            open.push_back(Bin{{}, w, tp, pp});
             b = &open.back();
         }
         b->ms.push_back(m);
@@ -780,7 +943,8 @@ int build_schedule(cae_ensemble *e, const cae_tuning *tn, const uint32_t *ids,
         it.first = (uint32_t)order.size();
         it.count = (uint32_t)b.ms.size();
         it.wpm_log2 = (uint32_t)__builtin_ctz(b.wpm);
-        it.stride = 2u * 64u * b.tpl + 8u;
+        it.stride = 2u * 64u * b.tpl + kScr;
+        it.pipe = b.pipe;
         for (uint32_t mm : b.ms) order.push_back(mm);
         items.push_back(it);
         lds_max = std::max(lds_max, it.count * it.stride * 4u);

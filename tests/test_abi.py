@@ -37,7 +37,7 @@ def test_struct_layouts(cae):
     assert C.sizeof(cae.Market) == 32
     assert C.sizeof(cae.State) == 72
     assert C.sizeof(cae.Sizes) == 32
-    assert C.sizeof(cae.Tuning) == 16 + 5 * cae.NUM_CLASSES
+    assert C.sizeof(cae.Tuning) == 16 + 6 * cae.NUM_CLASSES
 
 
 def test_strerror(cae):

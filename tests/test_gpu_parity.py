@@ -298,3 +298,37 @@ def test_queue_resets_between_launches():
     rst, rbk = O.run(descs, 3, 60)
     _assert_books(descs, bk, rbk)
     _assert_states(st, rst)
+
+
+@pytest.mark.parametrize("G", [2, 3, 4, 8, 16])
+def test_pipelined_pairs_exact(G):
+    """Pipelined pairs (one wave clears one market while the others generate the other's
+    orders), including an odd market left alone, give the oracle's books."""
+    descs = W.uniform(7, 100, 300, 9, 20, n_noise=150, n_mom=90, h=3)
+    tn = {"waves_per_group": G, "pipelined": {c: 1 for c in range(40)}}
+    st, bk, used = _run_gpu(descs, 21, [33, 17], tuning=tn)
+    assert used["pipelined"] and used["waves_per_group"] == G
+    rst, rbk = O.run(descs, 21, 50)
+    _assert_books(descs, bk, rbk)
+    _assert_states(st, rst)
+
+
+def test_pipelined_mixed_with_other_modes():
+    rng = np.random.default_rng(17)
+    n = 60
+    L = rng.choice([5, 64, 128, 256, 512, 1000], n)
+    A = rng.integers(1, 5000, n)
+    d = np.zeros(n, W.MARKET_DTYPE)
+    d["L"], d["A"], d["K"], d["Q"] = L, A, np.maximum(1, L // 16), rng.integers(1, 60, n)
+    d["n_noise"] = A // 2
+    d["n_mom"] = A // 3
+    d["h"] = np.minimum(2, L - 1)
+    from paper_2606_21784_amd import engine
+    cls = [engine.size_class(int(a), int(b)) for a, b in zip(L, A)]
+    tn = {"waves_per_group": 8,
+          "waves_per_market": {c: (1 if c % 3 == 0 else 4) for c in set(cls)},
+          "pipelined": {c: 1 for c in set(cls) if c % 3 == 1}}
+    st, bk, _ = _run_gpu(d, 77, [25], tuning=tn)
+    rst, rbk = O.run(d, 77, 25)
+    _assert_books(d, bk, rbk)
+    _assert_states(st, rst)
