@@ -154,6 +154,38 @@ def uneven_leg(reps=2):
     return out
 
 
+def ablation_leg(reps=3):
+    """The paper's ablation (section IV-I): the naive one-thread-per-market engine (book in
+    global memory, serial clearing) against the persistent engine, on the fixed workload and on
+    the paper's own fixed-workload shape (8192 markets, A = 256, L = 128, 500 steps; offsets
+    +-8 and quantities 1..10 here, the paper's values being unstated)."""
+    import numpy as np
+
+    from paper_2606_21784_amd import engine, workloads
+    out = {}
+    for w in (workloads.fixed(), workloads.paper_fixed()):
+        d, S = w["descs"], w["S"]
+        events = float(d["A"].astype(np.float64).sum()) * S
+        row = {}
+        for kind in ("persistent", "naive"):
+            ens = engine.Ensemble(d, w["seed"])
+            st, bk = ens.read_state(), ens.read_books()
+            best = None
+            for _ in range(reps if kind == "persistent" else 1):
+                ens.write_state(st, bk)
+                (ens.step if kind == "persistent" else ens.step_naive)(S)
+                ms = ens.last_step_ms()
+                best = ms if best is None else min(best, ms)
+            row[kind + "_ms"] = best
+            row[kind + "_events_per_s"] = events / (best * 1e-3)
+            ens.close()
+        row["speedup"] = row["naive_ms"] / row["persistent_ms"]
+        out[w["name"]] = row
+        log("ablation %s: persistent %.2f ms, naive %.1f ms (%.1fx)" %
+            (w["name"], row["persistent_ms"], row["naive_ms"], row["speedup"]))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -165,6 +197,8 @@ def main():
                     help="skip the uneven-ensemble leg (batched launch vs per-size launches)")
     ap.add_argument("--no-surrogate", action="store_true",
                     help="skip the calibration-surrogate leg (65536-draw sweep, training, judging)")
+    ap.add_argument("--no-ablation", action="store_true",
+                    help="skip the naive-engine ablation leg")
     ap.add_argument("--copy-calib", action="store_true",
                     help="after timing, copy 1 GiB device-to-device (counter calibration)")
     args = ap.parse_args()
@@ -254,6 +288,8 @@ def main():
             ok = np.array_equal(snap_bk[:n * 2 * L], rbk) if args.warmup == 1 else None
             result["cpu_baseline"]["gpu_matches_oracle"] = ok
     ens.close()
+    if not args.no_ablation:
+        result["ablation"] = ablation_leg()
     if not args.no_uneven:
         result["uneven"] = uneven_leg()
     if not args.no_surrogate:

@@ -177,8 +177,15 @@ int cae_write_state(cae_ensemble *e, const cae_state *host_state, uint32_t M,
 /* The schedule in use (as chosen at create).  */
 int cae_get_tuning(const cae_ensemble *e, cae_tuning *out);
 
-/* Duration in milliseconds of the last cae_step launch, from HIP events recorded on the
- * ensemble's stream around the kernel; waits for that launch to finish. */
+/* The same S steps as cae_step, computed by the naive engine of the paper's ablation
+ * (section IV-I, "Naive Custom CUDA"): one GPU thread per market, the book read and written in
+ * global memory at every step, clearing by serial loops over the L ticks.  Bit-identical results
+ * to cae_step (the same order rules and statistics); for comparison only.  Asynchronous; same
+ * errors as cae_step. */
+int cae_step_naive(cae_ensemble *e, uint32_t S);
+
+/* Duration in milliseconds of the last cae_step or cae_step_naive launch, from HIP events
+ * recorded on the ensemble's stream around the kernel; waits for that launch to finish. */
 int cae_last_step_ms(cae_ensemble *e, float *ms);
 
 /* Release the host handle.  Device buffers stay owned by the caller. */

@@ -60,7 +60,7 @@ class CaeError(RuntimeError):
 
 
 EXPORTS = ["cae_strerror", "cae_last_error", "cae_device_info", "cae_sizes", "cae_create",
-           "cae_step", "cae_read_books", "cae_read_state", "cae_write_state", "cae_get_tuning",
+           "cae_step", "cae_step_naive", "cae_read_books", "cae_read_state", "cae_write_state", "cae_get_tuning",
            "cae_last_step_ms", "cae_destroy", "cae_clear", "cae_mlp_sizes",
            "cae_mlp_refresh_weights", "cae_mlp_forward", "cae_mlp_backward", "cae_mlp_adam",
            "cae_mlp_loss_grad"]
@@ -84,6 +84,7 @@ def lib():
     L.cae_sizes.argtypes = [P, u32, P]
     L.cae_create.argtypes = [P, u32, u64, P, P, P, P, P]
     L.cae_step.argtypes = [P, u32]
+    L.cae_step_naive.argtypes = [P, u32]
     L.cae_read_books.argtypes = [P, P, u64]
     L.cae_read_state.argtypes = [P, P, u32]
     L.cae_write_state.argtypes = [P, P, u32, P, u64]

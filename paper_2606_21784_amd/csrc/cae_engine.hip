@@ -349,43 +349,76 @@ __device__ __forceinline__ ClearOut clear_dispatch(uint32_t *bk, uint32_t tpl, u
     return clear_wave<1>(bk, lane);
 }
 
+// The order rules of section III-C (this library's readings), shared by the persistent engine
+// and the naive one-thread-per-market engine so both produce identical books.
+struct OrderCtx {
+    int base;          // last - K
+    uint32_t span;     // 2K + 1
+    uint32_t Q;
+    int top;           // L - 1
+    uint32_t n_noise, mom_end;
+    int h;
+    uint32_t last, prev, s;
+};
+
+__device__ __forceinline__ OrderCtx order_ctx(const DevMarket &d, uint32_t s, uint32_t last, uint32_t prev)
+{
+    OrderCtx o;
+    o.base = (int)last - (int)d.K;
+    o.span = 2u * d.K + 1u;
+    o.Q = d.Q;
+    o.top = (int)d.L - 1;
+    o.n_noise = d.n_noise;
+    o.mom_end = d.n_noise + d.n_mom;
+    o.h = (int)d.h;
+    o.last = last;
+    o.prev = prev;
+    o.s = s;
+    return o;
+}
+
+__device__ __forceinline__ uint32_t order_qty(const OrderCtx &o, uint32_t w2) { return 1u + __umulhi(w2, o.Q); }
+
+// NOISE agent: fair coin for the side (w0), uniform offset in {-K..K} (w1); book word 2*tick+side.
+__device__ __forceinline__ uint32_t noise_word(const OrderCtx &o, uint32_t w0, uint32_t w1)
+{
+    const int tick = min(max(o.base + (int)__umulhi(w1, o.span), 0), o.top);
+    return 2u * (uint32_t)tick + (w0 >> 31);
+}
+
+// MOMENTUM (a < mom_end) or MAKER agent a.
+__device__ __forceinline__ uint32_t other_word(const OrderCtx &o, uint32_t a, uint32_t w0)
+{
+    uint32_t sell;
+    int tick;
+    if (a < o.mom_end) {  // MOMENTUM: follow the last price change, coin when unchanged
+        sell = o.last > o.prev ? 0u : (o.last < o.prev ? 1u : (w0 >> 31));
+        tick = (int)o.last + (sell ? -1 : 1);
+    } else {  // MAKER: buy when a + s is even, h ticks from the reference
+        sell = (a ^ o.s) & 1u;
+        tick = (int)o.last + (sell ? o.h : -o.h);
+    }
+    tick = min(max(tick, 0), o.top);
+    return 2u * (uint32_t)tick + sell;
+}
+
 // Every order of one market-step, added into the LDS book (interleaved pairs: word 2*tick+side).
 __device__ __forceinline__ void gen_orders(const DevMarket &d, uint32_t m, uint32_t s,
                                            uint32_t last, uint32_t prev, uint32_t key0,
                                            uint32_t key1, uint32_t t, uint32_t nthr, uint32_t *bk)
 {
     const PhiloxStep ph(s, m, key0, key1);
-    const int base = (int)last - (int)d.K;
-    const uint32_t span = 2u * d.K + 1u;
-    const uint32_t Q = d.Q;
-    const int top = (int)d.L - 1;
+    const OrderCtx o = order_ctx(d, s, last, prev);
     uint32_t a = t;
     for (; a < d.n_noise; a += nthr) {
         uint32_t w0, w1, w2;
         ph.words(a, w0, w1, w2);
-        const int tick = min(max(base + (int)__umulhi(w1, span), 0), top);
-        const uint32_t q = 1u + __umulhi(w2, Q);
-        atomicAdd(&bk[2u * (uint32_t)tick + (w0 >> 31)], q);
+        atomicAdd(&bk[noise_word(o, w0, w1)], order_qty(o, w2));
     }
-    if (a < d.A) {
-        const uint32_t mom_end = d.n_noise + d.n_mom;
-        const int h = (int)d.h;
-        for (; a < d.A; a += nthr) {
-            uint32_t w0, w1, w2;
-            ph.words(a, w0, w1, w2);
-            uint32_t sell;
-            int tick;
-            if (a < mom_end) {  // MOMENTUM
-                sell = last > prev ? 0u : (last < prev ? 1u : (w0 >> 31));
-                tick = (int)last + (sell ? -1 : 1);
-            } else {  // MAKER
-                sell = (a ^ s) & 1u;
-                tick = (int)last + (sell ? h : -h);
-            }
-            tick = min(max(tick, 0), top);
-            const uint32_t q = 1u + __umulhi(w2, Q);
-            atomicAdd(&bk[2u * (uint32_t)tick + sell], q);
-        }
+    for (; a < d.A; a += nthr) {
+        uint32_t w0, w1, w2;
+        ph.words(a, w0, w1, w2);
+        atomicAdd(&bk[other_word(o, a, w0)], order_qty(o, w2));
     }
 }
 
@@ -669,6 +702,88 @@ __global__ void __launch_bounds__(1024) cae_engine_kernel(const EngineArgs args)
             atomicExch(args.ctr + 1, 0u);
         }
     }
+}
+
+// The naive engine of the paper's ablation (section IV-I): one thread per market, the book in
+// global memory, every step's orders added one by one and the market cleared by serial loops
+// over the L ticks (sums, argmax, top-down / bottom-up fill).  Same orders and statistics as the
+// persistent engine; for comparison only.
+__global__ void __launch_bounds__(64) cae_naive_kernel(const EngineArgs args, uint32_t M)
+{
+    const uint32_t m = blockIdx.x * 64u + threadIdx.x;
+    if (m >= M) return;
+    const DevMarket d = args.desc[m];
+    uint32_t *bid = args.book + d.book_off;
+    uint32_t *ask = bid + d.L;
+    cae_state st = args.state[m];
+    const double *lnT = args.lnT + d.L;
+    for (uint32_t i = 0; i < args.S; ++i) {
+        const uint32_t s = (uint32_t)st.steps_done + i;
+        const PhiloxStep ph(s, d.id, args.k0, args.k1);
+        const OrderCtx o = order_ctx(d, s, st.last, st.prev);
+        for (uint32_t a = 0; a < d.A; ++a) {
+            uint32_t w0, w1, w2;
+            ph.words(a, w0, w1, w2);
+            const uint32_t w = a < d.n_noise ? noise_word(o, w0, w1) : other_word(o, a, w0);
+            const uint32_t q = order_qty(o, w2);
+            if (w & 1u) ask[w >> 1] += q;
+            else bid[w >> 1] += q;
+        }
+        uint32_t Tb = 0;
+        for (uint32_t p = 0; p < d.L; ++p) Tb += bid[p];
+        uint32_t best = 0, pbest = 0, cb = 0, ca = 0;
+        for (uint32_t p = 0; p < d.L; ++p) {
+            ca += ask[p];
+            const uint32_t V = min(Tb - cb, ca);
+            if (V > best) {
+                best = V;
+                pbest = p;
+            }
+            cb += bid[p];
+        }
+        if (best != 0) {
+            uint32_t rem = best;
+            for (int p = (int)d.L - 1; p >= 0 && rem; --p) {
+                const uint32_t f = min(bid[p], rem);
+                bid[p] -= f;
+                rem -= f;
+            }
+            rem = best;
+            for (uint32_t p = 0; p < d.L && rem; ++p) {
+                const uint32_t f = min(ask[p], rem);
+                ask[p] -= f;
+                rem -= f;
+            }
+        }
+        const uint32_t old_last = st.last;
+        st.prev = old_last;
+        if (best != 0) {
+            st.last = pbest;
+            st.n_trade += 1;
+            st.sum_vol += best;
+            st.sum_px += pbest;
+        }
+        int bb = -1, ba = -1;
+        for (int p = (int)d.L - 1; p >= 0; --p)
+            if (bid[p]) {
+                bb = p;
+                break;
+            }
+        for (uint32_t p = 0; p < d.L; ++p)
+            if (ask[p]) {
+                ba = (int)p;
+                break;
+            }
+        if (bb >= 0 && ba >= 0) {
+            st.sum_spread += (uint64_t)(ba - bb);
+            st.n_spread += 1;
+        }
+        const double r = lnT[st.last] - lnT[st.prev];
+        st.sum_r = st.sum_r + r;
+        st.sum_r2 = st.sum_r2 + r * r;
+    }
+    st.steps_done += args.S;
+    args.state[m] = st;
 }
 
 // One clearing pass over n books of L ticks: one wave per book, four books per workgroup.
@@ -1094,7 +1209,7 @@ int cae_create(const cae_market *desc, uint32_t M, uint64_t seed, const uint32_t
     return CAE_OK;
 }
 
-int cae_step(cae_ensemble *e, uint32_t S)
+static int step_impl(cae_ensemble *e, uint32_t S, bool naive)
 {
     if (!e) return fail(CAE_EINVAL, "NULL ensemble");
     if (S == 0) return CAE_OK;
@@ -1119,14 +1234,21 @@ int cae_step(cae_ensemble *e, uint32_t S)
     a.k0 = (uint32_t)e->seed;
     a.k1 = (uint32_t)(e->seed >> 32);
     HIP_TRY(hipEventRecord(e->ev0, e->stream));
-    hipLaunchKernelGGL(engine_fn(e->tpl_max), dim3(e->grid), dim3(e->waves_per_group * 64u), e->lds_bytes,
-                       e->stream, a);
+    if (naive)
+        hipLaunchKernelGGL(cae_naive_kernel, dim3((e->M + 63u) / 64u), dim3(64), 0, e->stream, a, e->M);
+    else
+        hipLaunchKernelGGL(engine_fn(e->tpl_max), dim3(e->grid), dim3(e->waves_per_group * 64u), e->lds_bytes,
+                           e->stream, a);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipEventRecord(e->ev1, e->stream));
     e->have_timing = true;
     for (uint32_t m = 0; m < e->M; ++m) e->steps_done[m] += S;
     return CAE_OK;
 }
+
+int cae_step(cae_ensemble *e, uint32_t S) { return step_impl(e, S, false); }
+
+int cae_step_naive(cae_ensemble *e, uint32_t S) { return step_impl(e, S, true); }
 
 int cae_last_step_ms(cae_ensemble *e, float *ms)
 {

@@ -128,6 +128,11 @@ class Ensemble:
         check("cae_step", lib().cae_step(self.handle, int(S)))
         self.steps += int(S)
 
+    def step_naive(self, S):
+        """The same S steps with the naive one-thread-per-market engine (ablation)."""
+        check("cae_step_naive", lib().cae_step_naive(self.handle, int(S)))
+        self.steps += int(S)
+
     def last_step_ms(self):
         ms = C.c_float()
         check("cae_last_step_ms", lib().cae_last_step_ms(self.handle, C.byref(ms)))

@@ -34,6 +34,32 @@ def fixed():
             "seed": 1, "S": 1000}
 
 
+def paper_fixed():
+    """The paper's fixed-workload shape (section IV-E, Table IV): 8192 markets, A = 256,
+    L = 128, 500 steps (1.049e9 events).  Offsets +-8 and quantities 1..10 (the paper does not
+    state its values), seed 2."""
+    return {"name": "paperfixed_M8192_L128_A256_S500", "descs": uniform(8192, 128, 256, 8, 10),
+            "seed": 2, "S": 500}
+
+
+def paper_market_sweep(M):
+    """The paper's market-count sweep shape (section IV-E, Table III top): A = 256, L = 128,
+    500 steps; offsets +-8 and quantities 1..10, seed 2."""
+    return {"name": "papersweep_M%d_L128_A256_S500" % M, "descs": uniform(M, 128, 256, 8, 10),
+            "seed": 2, "S": 500}
+
+
+def paper_agent_sweep(A):
+    """The paper's agent-count sweep shape (section IV-E, Table III bottom): 8192 markets,
+    L = 128, 500 steps; offsets +-8 and quantities 1..10, seed 2."""
+    return {"name": "paperagents_M8192_L128_A%d_S500" % A, "descs": uniform(8192, 128, A, 8, 10),
+            "seed": 2, "S": 500}
+
+
+PAPER_SWEEP_M = (64, 256, 1024, 4096, 16384)
+PAPER_SWEEP_A = (16, 64, 256, 1024)
+
+
 def market_sweep(M):
     """Market-count sweep point: L=512, A=4096, offsets +-32, qty 1..100, 10000 steps, seed 3."""
     return {"name": "sweep_M%d_L512_A4096_S10000" % M, "descs": uniform(M, 512, 4096, 32, 100),

@@ -332,3 +332,21 @@ def test_pipelined_mixed_with_other_modes():
     rst, rbk = O.run(d, 77, 25)
     _assert_books(d, bk, rbk)
     _assert_states(st, rst)
+
+
+@pytest.mark.parametrize("cfg", [(64, 128, 8, 10, 128, 0, 2), (100, 300, 9, 20, 150, 90, 3),
+                                 (1024, 700, 40, 50, 200, 300, 2), (1, 5, 0, 3, 2, 2, 0)])
+def test_naive_engine_is_bit_identical(cfg):
+    """The naive one-thread-per-market ablation engine gives the persistent engine's books."""
+    E = _engine()
+    L, A, K, Q, nn, nm, h = cfg
+    descs = W.uniform(70, L, A, K, Q, n_noise=nn, n_mom=nm, h=h)
+    ens = E.Ensemble(descs, 8)
+    ens.step_naive(20)
+    ens.step(10)
+    ens.step_naive(10)
+    st, bk = ens.read_state(), ens.read_books()
+    ens.close()
+    rst, rbk = O.run(descs, 8, 40)
+    _assert_books(descs, bk, rbk)
+    _assert_states(st, rst)
