@@ -134,9 +134,11 @@ def uneven_leg(reps=2):
     parts = []
     for c, idx in groups.items():
         wpm = tn["waves_per_market"][c]
+        pipe = tn.get("pipelined", {}).get(c, 0)
         parts.append(engine.Ensemble(d[idx], w["seed"], market_ids=idx,
-                                     tuning={"waves_per_group": max(4, wpm),
-                                             "waves_per_market": {c: wpm}}))
+                                     tuning={"waves_per_group": max(4 if not pipe else 8, wpm),
+                                             "waves_per_market": {c: wpm},
+                                             "pipelined": {c: pipe} if pipe else {}}))
     t_split = timed(parts, reps)
     for e in parts:
         e.close()
@@ -186,6 +188,76 @@ def ablation_leg(reps=3):
     return out
 
 
+# The paper's own results on an RTX 5090 for its shapes (its agent parameters and generator
+# differ from this engine's): Table III (market and agent sweeps), Table IV (fixed workload),
+# and the median per-step latency of section IV-I.
+PAPER_MARKET_SWEEP = {64: 3.61e9, 256: 1.35e10, 1024: 3.69e10, 4096: 4.73e10, 16384: 5.39e10}
+PAPER_AGENT_SWEEP = {16: 8.41e9, 64: 2.84e10, 256: 5.16e10, 1024: 5.47e10}
+PAPER_FIXED = 5.203e10
+PAPER_STEP_LATENCY_US = 22.1
+
+
+def tuned_time(w, reps=2):
+    """Autotuned schedule, then the best of `reps` timed launches of S steps (rewinding the
+    state between launches, outside the timed region).  Returns (ms, events/s, schedule)."""
+    import numpy as np
+
+    from paper_2606_21784_amd import autotune, engine
+    d, S = w["descs"], w["S"]
+    events = float(d["A"].astype(np.float64).sum()) * S
+    tn = autotune.tune(d, seed=w["seed"], S_probe=min(40, S))
+    ens = engine.Ensemble(d, w["seed"], tuning=tn)
+    st, bk = ens.read_state(), ens.read_books()
+    times = []
+    for _ in range(reps):
+        ens.write_state(st, bk)
+        ens.step(S)
+        times.append(ens.last_step_ms())
+    used = ens.tuning()
+    ens.close()
+    ms = min(times)
+    sched = {"waves_per_group": used["waves_per_group"],
+             "waves_per_market": sorted(set(used["waves_per_market"].values())),
+             "pipelined": bool(used["pipelined"])}
+    return ms, events / (ms * 1e-3), sched, times
+
+
+def sweeps_leg():
+    """The paper's sweep shapes and latency figure, and the 10000-step market-count sweep."""
+    import numpy as np
+
+    from paper_2606_21784_amd import workloads
+    out = {"paper_market_sweep": {}, "paper_agent_sweep": {}, "market_sweep": {}}
+    for M in workloads.PAPER_SWEEP_M:
+        ms, ev, sched, _ = tuned_time(workloads.paper_market_sweep(M))
+        out["paper_market_sweep"][str(M)] = {"ms": ms, "events_per_s": ev, "schedule": sched,
+                                             "paper_rtx5090_events_per_s": PAPER_MARKET_SWEEP[M]}
+        log("paper market sweep M=%d: %.3f ms, %.3g events/s" % (M, ms, ev))
+    for A in workloads.PAPER_SWEEP_A:
+        ms, ev, sched, _ = tuned_time(workloads.paper_agent_sweep(A))
+        out["paper_agent_sweep"][str(A)] = {"ms": ms, "events_per_s": ev, "schedule": sched,
+                                            "paper_rtx5090_events_per_s": PAPER_AGENT_SWEEP[A]}
+        log("paper agent sweep A=%d: %.3f ms, %.3g events/s" % (A, ms, ev))
+    w = workloads.paper_fixed()
+    ms, ev, sched, _ = tuned_time(w)
+    out["paper_fixed"] = {"workload": w["name"], "ms": ms, "events_per_s": ev, "schedule": sched,
+                          "paper_rtx5090_events_per_s": PAPER_FIXED}
+    # per-step latency: wall time of a launch / its steps, 11 launches, median (section IV-I)
+    w = workloads.paper_market_sweep(4096)
+    _, _, sched, times = tuned_time(w, reps=11)
+    lat = [1e3 * t / w["S"] for t in times]
+    out["step_latency"] = {"workload": w["name"], "median_us": float(np.median(lat)),
+                           "min_us": float(np.min(lat)), "max_us": float(np.max(lat)),
+                           "paper_rtx5090_median_us": PAPER_STEP_LATENCY_US, "schedule": sched}
+    log("step latency %s: median %.2f us" % (w["name"], out["step_latency"]["median_us"]))
+    for M in workloads.MARKET_SWEEP_M:
+        ms, ev, sched, _ = tuned_time(workloads.market_sweep(M), reps=1)
+        out["market_sweep"][str(M)] = {"ms": ms, "events_per_s": ev, "schedule": sched,
+                                       "step_latency_us": 1e3 * ms / 10000}
+        log("market sweep M=%d: %.1f ms, %.3g events/s" % (M, ms, ev))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -197,6 +269,8 @@ def main():
                     help="skip the uneven-ensemble leg (batched launch vs per-size launches)")
     ap.add_argument("--no-surrogate", action="store_true",
                     help="skip the calibration-surrogate leg (65536-draw sweep, training, judging)")
+    ap.add_argument("--no-sweeps", action="store_true",
+                    help="skip the sweep leg (paper shapes, step latency, market-count sweep)")
     ap.add_argument("--no-ablation", action="store_true",
                     help="skip the naive-engine ablation leg")
     ap.add_argument("--copy-calib", action="store_true",
@@ -218,10 +292,15 @@ def main():
     d = w["descs"]
     M, L, A, S = len(d), int(d["L"][0]), int(d["A"][0]), w["S"]
     events = float(np.sum(d["A"].astype(np.float64))) * S
-    ens = engine.Ensemble(d, w["seed"])
+    from paper_2606_21784_amd import autotune
+    t0 = time.perf_counter()
+    tn = autotune.tune(d, seed=w["seed"], S_probe=40)
+    tune_s = time.perf_counter() - t0
+    ens = engine.Ensemble(d, w["seed"], tuning=tn)
     sched = ens.tuning()
     sched = {"waves_per_group": sched["waves_per_group"], "groups_per_cu": sched["groups_per_cu"],
-             "waves_per_market": sorted(set(sched["waves_per_market"].values()))}
+             "waves_per_market": sorted(set(sched["waves_per_market"].values())),
+             "pipelined": bool(sched["pipelined"]), "autotune_s": tune_s}
     log("schedule:", json.dumps(sched))
 
     for _ in range(args.warmup):
@@ -290,6 +369,8 @@ def main():
     ens.close()
     if not args.no_ablation:
         result["ablation"] = ablation_leg()
+    if not args.no_sweeps:
+        result["sweeps"] = sweeps_leg()
     if not args.no_uneven:
         result["uneven"] = uneven_leg()
     if not args.no_surrogate:

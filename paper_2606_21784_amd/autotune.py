@@ -1,8 +1,10 @@
 """Autotuner for the persistent engine's schedule.
 
-The engine's schedule has three knobs (``cae_tuning`` in include/cae.h):
+The engine's schedule has these knobs (``cae_tuning`` in include/cae.h):
   * waves per market, per size class (class = L bucket x A bucket): how many wave64s generate
     one market's orders; the rest of the workgroup's waves belong to other markets;
+  * pipelined, per size class: markets run in pairs that share all of a workgroup's waves in
+    alternating phases (one wave clears one market while the others generate the other's);
   * waves per workgroup: how many markets of one class share a workgroup (in lock-step when a
     market spans more than one wave) and therefore how the workgroup's LDS is partitioned into
     market slices;
@@ -21,6 +23,7 @@ import numpy as np
 from . import engine
 
 WPM_CANDIDATES = (1, 2, 4, 8, 16)
+PIPE_GROUPS = (4, 8)
 GROUP_CANDIDATES = (4, 8, 16)
 
 
@@ -68,36 +71,45 @@ def tune(descs, seed=0, S_probe=40, min_markets=None, cache=None, arch="gfx950",
         min_markets = 4 * engine.device_info()["num_cu"]
     cls = classes_of(descs)
     wpm = {}
+    pipe_c = {}
     cost = {}
     t0 = time.perf_counter()
     for c in sorted(set(cls.tolist())):
         key = str(c)
         if key in cached:
             wpm[c] = int(cached[key]["waves_per_market"])
+            pipe_c[c] = bool(cached[key].get("pipelined", False))
             cost[c] = float(cached[key]["ns_per_market_step"])
             continue
         probe = _probe_set(descs, np.nonzero(cls == c)[0], min_markets, rng)
         events = float(probe["A"].astype(np.float64).sum()) * S_probe
+        cands = [(w, False, max(4, w)) for w in WPM_CANDIDATES] + [(1, True, G) for G in PIPE_GROUPS]
         best = None
-        for w in WPM_CANDIDATES:
-            tn = {"waves_per_group": max(4, w), "waves_per_market": {int(c): w}}
+        for w, pipe, G in cands:
+            tn = {"waves_per_group": G, "waves_per_market": {int(c): w}}
+            if pipe:
+                tn["pipelined"] = {int(c): 1}
             ms = _time_launch(probe, seed, tn, S_probe)
             if log:
-                log("class %2d (L<=%4d, A~2^%d) wpm %2d: %.3f ms, %.3g events/s" %
-                    (c, 64 << (c // 8), 6 + c % 8, w, ms, events / (ms * 1e-3)))
-            if best is None or ms < best[1]:
-                best = (w, ms)
+                log("class %2d (L<=%4d, A~2^%d) %s: %.3f ms, %.3g events/s" %
+                    (c, 64 << (c // 8), 6 + c % 8, ("pipelined G=%d" % G) if pipe else "wpm %2d" % w,
+                     ms, events / (ms * 1e-3)))
+            if best is None or ms < best[3]:
+                best = (w, pipe, G, ms)
         wpm[c] = best[0]
+        pipe_c[c] = best[1]
         # per market-step cost when the class fills the GPU alone
-        cost[c] = best[1] * 1e6 / (len(probe) * S_probe) * engine.device_info()["num_cu"]
-        cached[key] = {"waves_per_market": wpm[c], "ns_per_market_step": cost[c]}
+        cost[c] = best[3] * 1e6 / (len(probe) * S_probe) * engine.device_info()["num_cu"]
+        cached[key] = {"waves_per_market": wpm[c], "pipelined": bool(pipe_c[c]),
+                       "ns_per_market_step": cost[c]}
     # waves per workgroup on the whole ensemble
     wmax = max(wpm.values())
     best_g = None
     for G in GROUP_CANDIDATES:
         if G < wmax:
             continue
-        tn = {"waves_per_group": G, "waves_per_market": {int(c): w for c, w in wpm.items()}}
+        tn = {"waves_per_group": G, "waves_per_market": {int(c): w for c, w in wpm.items()},
+              "pipelined": {int(c): 1 for c, p in pipe_c.items() if p}}
         ms = _time_launch(descs, seed, tn, max(4, S_probe // 4), reps=1)
         if log:
             log("waves_per_group %2d: %.3f ms" % (G, ms))
@@ -114,6 +126,7 @@ def tune(descs, seed=0, S_probe=40, min_markets=None, cache=None, arch="gfx950",
             json.dump(allc, f, indent=1, sort_keys=True)
     result = {"waves_per_group": best_g[0],
               "waves_per_market": {int(c): int(w) for c, w in wpm.items()},
+              "pipelined": {int(c): 1 for c, p in pipe_c.items() if p},
               "class_cost_ns": {int(c): float(v) for c, v in cost.items()},
               "tune_seconds": time.perf_counter() - t0}
     return result
