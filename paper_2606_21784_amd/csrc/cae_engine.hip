@@ -594,20 +594,30 @@ __device__ __forceinline__ void run_pair(const EngineArgs &args, const Item &ite
     __syncthreads();
     const uint32_t S = args.S;
     const uint32_t nph = 2u * S + (npair == 2u ? 1u : 0u);
-    uint32_t c = 0;  // clearing wave of this phase: p mod G
+    // generator index of this wave, (wave - c - 1) mod G for clearing wave c = p mod G; it steps
+    // down by one per phase, and the clearing wave is the one at G - 1
+    uint32_t gidx = (wave + G - 1u) % G;
     for (uint32_t p = 0; p < nph; ++p) {
         const uint32_t X = p & 1u, Y = X ^ 1u;
-        if (wave == c) {
+        if (gidx == G - 1u) {
             if (p >= 1u && Y < npair) {
                 uint32_t *bk = lds + Y * item.stride;
                 uint32_t *scr = bk + item.stride - kScr;
                 const DevMarket &dy = Y ? dB : dA;
                 const ClearOut co = clear_dispatch<TPL_MAX>(bk, dy.tpl, lane);
-                const uint32_t last0 = lds_u32(scr);
-                uint64_t n_trade = lds_u64(scr + 4), sum_vol = lds_u64(scr + 6), sum_px = lds_u64(scr + 8);
-                uint64_t sum_spread = lds_u64(scr + 10), n_spread = lds_u64(scr + 12);
-                const double sum_r = __longlong_as_double((long long)lds_u64(scr + 14));
-                const double sum_r2 = __longlong_as_double((long long)lds_u64(scr + 16));
+                const uint4 s0 = *reinterpret_cast<const uint4 *>(scr);       // last, prev, steps
+                const uint4 s1 = *reinterpret_cast<const uint4 *>(scr + 4);   // n_trade, sum_vol
+                const uint4 s2 = *reinterpret_cast<const uint4 *>(scr + 8);   // sum_px, sum_spread
+                const uint4 s3 = *reinterpret_cast<const uint4 *>(scr + 12);  // n_spread, sum_r
+                const uint2 s4 = *reinterpret_cast<const uint2 *>(scr + 16);  // sum_r2
+                auto u = [](uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); };
+                auto u64 = [&](uint32_t lo, uint32_t hi) { return ((uint64_t)u(hi) << 32) | u(lo); };
+                const uint32_t last0 = u(s0.x);
+                uint64_t n_trade = u64(s1.x, s1.y), sum_vol = u64(s1.z, s1.w);
+                uint64_t sum_px = u64(s2.x, s2.y), sum_spread = u64(s2.z, s2.w);
+                uint64_t n_spread = u64(s3.x, s3.y);
+                const double sum_r = __longlong_as_double((long long)u64(s3.z, s3.w));
+                const double sum_r2 = __longlong_as_double((long long)u64(s4.x, s4.y));
                 uint32_t last = last0;
                 if (co.v != 0) {
                     last = co.p;
@@ -635,15 +645,15 @@ __device__ __forceinline__ void run_pair(const EngineArgs &args, const Item &ite
             }
         } else if (p < 2u * S && X < npair) {
             uint32_t *bk = lds + X * item.stride;
-            const uint32_t *scr = bk + item.stride - kScr;
-            const uint32_t last = lds_u32(scr), prev = lds_u32(scr + 1);
-            const uint32_t s = (uint32_t)lds_u64(scr + 2) + (p >> 1);
-            const uint32_t gidx = (wave + G - c - 1u) % G;  // 0 .. G-2
+            const uint4 s0 = *reinterpret_cast<const uint4 *>(bk + item.stride - kScr);
+            const uint32_t last = (uint32_t)__builtin_amdgcn_readfirstlane((int)s0.x);
+            const uint32_t prev = (uint32_t)__builtin_amdgcn_readfirstlane((int)s0.y);
+            const uint32_t s = (uint32_t)__builtin_amdgcn_readfirstlane((int)s0.z) + (p >> 1);
             const DevMarket &dx = X ? dB : dA;
             gen_orders(dx, dx.id, s, last, prev, args.k0, args.k1, (gidx << 6) | lane, (G - 1u) << 6, bk);
         }
         __syncthreads();
-        c = (c + 1u == G) ? 0u : c + 1u;
+        gidx = gidx == 0u ? G - 1u : gidx - 1u;
     }
 #pragma unroll
     for (uint32_t x = 0; x < 2; ++x) {
