@@ -121,7 +121,7 @@ def uneven_leg(reps=2):
         return best
 
     t0 = time.perf_counter()
-    tn = autotune.tune(d, seed=w["seed"], S_probe=40, log=log)
+    tn = autotune.tune(d, seed=w["seed"], log=log)
     tune_s = time.perf_counter() - t0
     ens = engine.Ensemble(d, w["seed"], tuning=tn)
     t_batched = timed([ens], reps)
@@ -205,7 +205,7 @@ def tuned_time(w, reps=2):
     from paper_2606_21784_amd import autotune, engine
     d, S = w["descs"], w["S"]
     events = float(d["A"].astype(np.float64).sum()) * S
-    tn = autotune.tune(d, seed=w["seed"], S_probe=min(40, S))
+    tn = autotune.tune(d, seed=w["seed"])
     ens = engine.Ensemble(d, w["seed"], tuning=tn)
     st, bk = ens.read_state(), ens.read_books()
     times = []
@@ -294,7 +294,7 @@ def main():
     events = float(np.sum(d["A"].astype(np.float64))) * S
     from paper_2606_21784_amd import autotune
     t0 = time.perf_counter()
-    tn = autotune.tune(d, seed=w["seed"], S_probe=40)
+    tn = autotune.tune(d, seed=w["seed"])
     tune_s = time.perf_counter() - t0
     ens = engine.Ensemble(d, w["seed"], tuning=tn)
     sched = ens.tuning()

@@ -31,19 +31,37 @@ def classes_of(descs):
     return np.array([engine.size_class(int(L), int(A)) for L, A in zip(descs["L"], descs["A"])])
 
 
-def _time_launch(descs, seed, tuning, S, reps=2):
+def _time_launch(descs, seed, tuning, S, reps=3):
+    """Best kernel time (ms) of `reps` launches of S steps, each from the same opening state
+    (rewound outside the timed region) after one untimed launch."""
     ens = engine.Ensemble(descs, seed, tuning=tuning)
     try:
+        st, bk = ens.read_state(), ens.read_books()
         ens.step(S)
         ens.last_step_ms()
         best = None
         for _ in range(reps):
+            ens.write_state(st, bk)
             ens.step(S)
             ms = ens.last_step_ms()
             best = ms if best is None else min(best, ms)
         return best
     finally:
         ens.close()
+
+
+# Probe launches are sized to about this many agent events (roughly a millisecond), so that
+# launch overhead and timer resolution stay below the differences between candidates.
+PROBE_EVENTS = 5e8
+
+
+def probe_steps(descs, S_min=20, S_max=1000, events=PROBE_EVENTS):
+    """Steps per probe launch: about `events` agent events, within [S_min, S_max] and within
+    the 32-bit book guard ((S + 1) A Q < 2^32 for the untimed launch plus one timed one)."""
+    per_step = float(descs["A"].astype(np.float64).sum())
+    S = int(np.clip(round(events / max(per_step, 1.0)), S_min, S_max))
+    guard = (2**32 - 1) // int((descs["A"].astype(np.int64) * descs["Q"].astype(np.int64)).max())
+    return int(max(1, min(S, guard // 2 - 1)))
 
 
 def _probe_set(descs, idx, min_markets, rng):
@@ -56,11 +74,12 @@ def _probe_set(descs, idx, min_markets, rng):
     return np.ascontiguousarray(descs[pick])
 
 
-def tune(descs, seed=0, S_probe=40, min_markets=None, cache=None, arch="gfx950", log=None):
+def tune(descs, seed=0, S_probe=None, min_markets=None, cache=None, arch="gfx950", log=None):
     """Return a tuning dict for ``engine.Ensemble(..., tuning=...)``.
 
-    descs: the ensemble's market descriptors; S_probe: steps per timed probe launch;
-    min_markets: markets per class probe (default 4 per CU); cache: optional JSON path.
+    descs: the ensemble's market descriptors; S_probe: steps per timed probe launch (default:
+    sized by probe_steps); min_markets: markets per class probe (default 4 per CU); cache:
+    optional JSON path.
     """
     rng = np.random.default_rng(0)
     cached = {}
@@ -82,14 +101,15 @@ def tune(descs, seed=0, S_probe=40, min_markets=None, cache=None, arch="gfx950",
             cost[c] = float(cached[key]["ns_per_market_step"])
             continue
         probe = _probe_set(descs, np.nonzero(cls == c)[0], min_markets, rng)
-        events = float(probe["A"].astype(np.float64).sum()) * S_probe
+        Sp = S_probe or probe_steps(probe)
+        events = float(probe["A"].astype(np.float64).sum()) * Sp
         cands = [(w, False, max(4, w)) for w in WPM_CANDIDATES] + [(1, True, G) for G in PIPE_GROUPS]
         best = None
         for w, pipe, G in cands:
             tn = {"waves_per_group": G, "waves_per_market": {int(c): w}}
             if pipe:
                 tn["pipelined"] = {int(c): 1}
-            ms = _time_launch(probe, seed, tn, S_probe)
+            ms = _time_launch(probe, seed, tn, Sp)
             if log:
                 log("class %2d (L<=%4d, A~2^%d) %s: %.3f ms, %.3g events/s" %
                     (c, 64 << (c // 8), 6 + c % 8, ("pipelined G=%d" % G) if pipe else "wpm %2d" % w,
@@ -99,7 +119,7 @@ def tune(descs, seed=0, S_probe=40, min_markets=None, cache=None, arch="gfx950",
         wpm[c] = best[0]
         pipe_c[c] = best[1]
         # per market-step cost when the class fills the GPU alone
-        cost[c] = best[3] * 1e6 / (len(probe) * S_probe) * engine.device_info()["num_cu"]
+        cost[c] = best[3] * 1e6 / (len(probe) * Sp) * engine.device_info()["num_cu"]
         cached[key] = {"waves_per_market": wpm[c], "pipelined": bool(pipe_c[c]),
                        "ns_per_market_step": cost[c]}
     # waves per workgroup on the whole ensemble
@@ -110,7 +130,7 @@ def tune(descs, seed=0, S_probe=40, min_markets=None, cache=None, arch="gfx950",
             continue
         tn = {"waves_per_group": G, "waves_per_market": {int(c): w for c, w in wpm.items()},
               "pipelined": {int(c): 1 for c, p in pipe_c.items() if p}}
-        ms = _time_launch(descs, seed, tn, max(4, S_probe // 4), reps=1)
+        ms = _time_launch(descs, seed, tn, S_probe or probe_steps(descs))
         if log:
             log("waves_per_group %2d: %.3f ms" % (G, ms))
         if best_g is None or ms < best_g[1]:
