@@ -17,7 +17,7 @@ STATE_DTYPE = np.dtype([
     ("last", np.uint32), ("prev", np.uint32), ("steps_done", np.uint64),
     ("n_trade", np.uint64), ("sum_vol", np.uint64), ("sum_px", np.uint64),
     ("sum_spread", np.uint64), ("n_spread", np.uint64),
-    ("sum_r", np.float64), ("sum_r2", np.float64),
+    ("sum_r", np.float64), ("sum_r2", np.float64), ("ref2", np.uint32), ("reserved", np.uint32),
 ])
 MARKET_DTYPE = np.dtype([
     ("L", np.uint32), ("A", np.uint32), ("K", np.uint32), ("Q", np.uint32),
@@ -45,9 +45,14 @@ def lib():
         L.orc_market_run.restype = i32
         L.orc_run.argtypes = [P, P, P, u32, u64, u32, P, P, i32]
         L.orc_run.restype = i32
+        L.orc_market_run_traced.argtypes = [P, u32, u64, u32, P, P, P, P, P]
+        L.orc_market_run_traced.restype = i32
+        L.orc_run_traced.argtypes = [P, P, P, u32, u64, u32, P, P, i32, P, P, u64]
+        L.orc_run_traced.restype = i32
         L.orc_clear_batch.argtypes = [u32, u32, P, P, P]
         L.orc_philox_batch.argtypes = [u32, P, P, P]
         L.orc_orders.argtypes = [P, u32, u64, u32, u32, u32, P, P, P]
+        L.orc_orders_mid.argtypes = [P, u32, u64, u32, u32, u32, P, P, P]
         L.orc_state_size.restype = u32
         L.orc_market_size.restype = u32
         assert L.orc_state_size() == STATE_DTYPE.itemsize
@@ -84,6 +89,14 @@ def urange(w, n):
     return int(lib().orc_range(int(w) & 0xFFFFFFFF, int(n)))
 
 
+MODEL_LAST, MODEL_MID = 0, 1
+
+
+def model_flags(model=MODEL_LAST, p_mkt16=0):
+    """Descriptor flags: agent model in bits 0-7, P_mkt (units of 2^-16) in bits 16-31."""
+    return (int(p_mkt16) << 16) | int(model)
+
+
 def market(L, A, K, Q, n_noise=None, n_mom=0, h=2, flags=0):
     d = np.zeros(1, MARKET_DTYPE)
     d["L"], d["A"], d["K"], d["Q"] = L, A, K, Q
@@ -104,6 +117,17 @@ def orders(desc, m, seed, s, last, prev):
     tick = np.zeros(A, np.uint32)
     qty = np.zeros(A, np.uint32)
     lib().orc_orders(_p(desc), m, seed, s, last, prev, _p(side), _p(tick), _p(qty))
+    return side, tick, qty
+
+
+def orders_mid(desc, m, seed, s, mid2, mid2_prev):
+    """Mid-price-model orders of every agent at step s, for mid = mid2 / 2 and previous mid
+    mid2_prev / 2."""
+    A = int(desc["A"][0])
+    side = np.zeros(A, np.uint32)
+    tick = np.zeros(A, np.uint32)
+    qty = np.zeros(A, np.uint32)
+    lib().orc_orders_mid(_p(desc), m, seed, s, mid2, mid2_prev, _p(side), _p(tick), _p(qty))
     return side, tick, qty
 
 
@@ -159,10 +183,12 @@ def book_offsets(descs):
     return off, int(2 * L.sum())
 
 
-def run(descs, seed, S, ids=None, states=None, book=None, nthreads=None):
+def run(descs, seed, S, ids=None, states=None, book=None, nthreads=None, trace=False):
     """S steps of several markets.  descs[i] describes market ids[i] (default: i).
 
-    Books are packed per market (bid[L] then ask[L]) in descs order."""
+    Books are packed per market (bid[L] then ask[L]) in descs order.  With trace=True also
+    returns the per-step series: price[i, t] = the last clearing tick after step t of this call,
+    volume[i, t] = the volume executed in it (uint64)."""
     descs = np.ascontiguousarray(descs, dtype=MARKET_DTYPE)
     n = len(descs)
     ids = np.arange(n, dtype=np.uint32) if ids is None else np.ascontiguousarray(ids, dtype=np.uint32)
@@ -176,9 +202,17 @@ def run(descs, seed, S, ids=None, states=None, book=None, nthreads=None):
     bk = np.zeros(words, np.uint32) if book is None else np.array(book, dtype=np.uint32)
     if nthreads is None:
         nthreads = min(os.cpu_count() or 1, 16)
-    rc = lib().orc_run(_p(descs), _p(ids), _p(off), n, seed, S, _p(states), _p(bk), nthreads)
+    if trace:
+        price = np.zeros((n, S), np.uint32)
+        vol = np.zeros((n, S), np.uint64)
+        rc = lib().orc_run_traced(_p(descs), _p(ids), _p(off), n, seed, S, _p(states), _p(bk),
+                                  nthreads, _p(price), _p(vol), S)
+    else:
+        rc = lib().orc_run(_p(descs), _p(ids), _p(off), n, seed, S, _p(states), _p(bk), nthreads)
     if rc != 0:
         raise ValueError("oracle run failed (%d)" % rc)
+    if trace:
+        return states, bk, price, vol
     return states, bk
 
 

@@ -85,8 +85,11 @@ typedef struct {
     uint32_t n_noise; /* agents [0, n_noise) are NOISE                                      */
     uint32_t n_mom;   /* agents [n_noise, n_noise + n_mom) are MOMENTUM, the rest MAKER     */
     uint32_t h;       /* maker half-spread in ticks                                         */
-    uint32_t flags;   /* reserved, 0                                                        */
+    uint32_t flags;   /* bits 0-7: agent model (ORC_MODEL_*); bits 16-31: the probability
+                         P_mkt of a marketable order in units of 2^-16 (mid-price model only) */
 } orc_market;
+
+enum { ORC_MODEL_LAST = 0, ORC_MODEL_MID = 1 };
 
 typedef struct {
     uint32_t last;        /* last clearing tick (agents' reference price)                  */
@@ -99,6 +102,8 @@ typedef struct {
     uint64_t n_spread;    /* number of such steps                                          */
     double sum_r;         /* sum of log returns ln(L+last) - ln(L+prev)                    */
     double sum_r2;        /* sum of their squares                                          */
+    uint32_t ref2;        /* twice the reference price the agents used in the latest step  */
+    uint32_t reserved;    /* 0                                                             */
 } orc_state;
 
 enum { ORC_BUY = 0, ORC_SELL = 1 };
@@ -108,6 +113,7 @@ void orc_initial_state(const orc_market *d, orc_state *st)
     memset(st, 0, sizeof(*st));
     st->last = d->L / 2;
     st->prev = d->L / 2;
+    st->ref2 = 2u * (d->L / 2);
 }
 
 static uint32_t clamp_tick(int64_t t, uint32_t L)
@@ -150,6 +156,53 @@ void orc_agent_order(const orc_market *d, uint32_t m, uint64_t seed, uint32_t a,
     }
     *side = sd;
     *tick = clamp_tick(t, d->L);
+    *qty = 1u + orc_range(w[2], d->Q);
+}
+
+/* The paper's own agent rules (section III-C, "State Retrieval" and "Agent Strategy Classes"):
+ * the reference is the mid-price of the resting book, mid = (bb + ba) / 2 when both sides are
+ * quoted, else the last clearing price; round(x) is floor(x + 1/2).  mid and mid_prev are
+ * half-integers, passed as doubles.
+ *   NOISE: fair coin for the side; price round(mid + eta) with eta = K (2u - 1), u = w1 / 2^32,
+ *          so eta is uniform on [-K, K).  With probability P_mkt (u3 = w3 / 2^32 < P_mkt) the
+ *          order is marketable: price L-1 for a buy, 0 for a sell.
+ *   MOMENTUM: side = sign(mid - mid_prev), the coin when the mid did not move; price
+ *          round(mid + 1) for a buy, round(mid - 1) for a sell; marketable like NOISE.
+ *   MAKER: buys when (a + s) is even; price round(mid - h) for a bid, round(mid + h) for an
+ *          ask; never marketable.
+ * Every price is then clamped to the grid.  Quantities as in the last-tick model.  All the
+ * doubles involved are exact: K and h are below 2^10 and u has 32 significant bits. */
+void orc_agent_order_mid(const orc_market *d, uint32_t m, uint64_t seed, uint32_t a, uint32_t s,
+                         double mid, double mid_prev, uint32_t *side, uint32_t *tick, uint32_t *qty)
+{
+    uint32_t ctr[4] = {s, a, m, 0u};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t w[4];
+    orc_philox4x32_10(ctr, key, w);
+
+    const double two32 = 4294967296.0;
+    uint32_t coin = (w[0] < 0x80000000u) ? ORC_BUY : ORC_SELL;
+    double p_mkt = (double)(d->flags >> 16) / 65536.0;
+    int marketable = ((double)w[3] / two32) < p_mkt;
+    uint32_t sd;
+    double price;
+    if (a < d->n_noise) {
+        double eta = (double)d->K * (2.0 * ((double)w[1] / two32) - 1.0);
+        sd = coin;
+        price = floor(mid + eta + 0.5);
+    } else if (a < d->n_noise + d->n_mom) {
+        if (mid > mid_prev) sd = ORC_BUY;
+        else if (mid < mid_prev) sd = ORC_SELL;
+        else sd = coin;
+        price = floor(mid + (sd == ORC_BUY ? 1.0 : -1.0) + 0.5);
+    } else {
+        sd = (((uint64_t)a + (uint64_t)s) % 2u == 0u) ? ORC_BUY : ORC_SELL;
+        price = floor(mid + (sd == ORC_BUY ? -(double)d->h : (double)d->h) + 0.5);
+        marketable = 0;
+    }
+    if (marketable) price = (sd == ORC_BUY) ? (double)d->L - 1.0 : 0.0;
+    *side = sd;
+    *tick = clamp_tick((int64_t)price, d->L);
     *qty = 1u + orc_range(w[2], d->Q);
 }
 
@@ -237,10 +290,24 @@ void orc_market_step(const orc_market *d, uint32_t m, uint64_t seed, orc_state *
                      const uint32_t *agent_order)
 {
     uint32_t s = (uint32_t)st->steps_done;
+    uint32_t model = d->flags & 0xFFu;
+    double mid = (double)st->last, mid_prev = 0.5 * (double)st->ref2;
+    if (model == ORC_MODEL_MID) {
+        /* state retrieval on the resting book: best bid, best ask, mid-price */
+        int64_t bb = -1, ba = -1;
+        for (int64_t p = (int64_t)d->L - 1; p >= 0; --p)
+            if (bid[p] > 0) { bb = p; break; }
+        for (uint32_t p = 0; p < d->L; ++p)
+            if (ask[p] > 0) { ba = p; break; }
+        if (bb >= 0 && ba >= 0) mid = 0.5 * (double)(bb + ba);
+    }
     for (uint32_t i = 0; i < d->A; ++i) {
         uint32_t a = agent_order ? agent_order[i] : i;
         uint32_t side, tick, qty;
-        orc_agent_order(d, m, seed, a, s, st->last, st->prev, &side, &tick, &qty);
+        if (model == ORC_MODEL_MID)
+            orc_agent_order_mid(d, m, seed, a, s, mid, mid_prev, &side, &tick, &qty);
+        else
+            orc_agent_order(d, m, seed, a, s, st->last, st->prev, &side, &tick, &qty);
         if (side == ORC_BUY) bid[tick] += qty;
         else ask[tick] += qty;
     }
@@ -248,21 +315,39 @@ void orc_market_step(const orc_market *d, uint32_t m, uint64_t seed, orc_state *
     uint64_t vstar;
     orc_clear(d->L, bid, ask, &pstar, &vstar);
     orc_update_stats(d->L, bid, ask, pstar, vstar, lnp, st);
+    st->ref2 = (uint32_t)(2.0 * mid);  /* the reference of this step (the last price, or the mid) */
 }
 
-/* S steps of one market (book = bid[L] followed by ask[L]). */
-int orc_market_run(const orc_market *d, uint32_t m, uint64_t seed, uint32_t S, orc_state *st,
-                   uint32_t *book, const uint32_t *agent_order)
+/* S steps of one market (book = bid[L] followed by ask[L]).  When tr_price / tr_vol are not
+ * NULL they receive, for every step i of this call, the reference (last clearing) tick after the
+ * step and the volume V* executed in it: the per-step price and volume series that the paper's
+ * market-dynamics experiments read (section IV-J). */
+int orc_market_run_traced(const orc_market *d, uint32_t m, uint64_t seed, uint32_t S, orc_state *st,
+                          uint32_t *book, const uint32_t *agent_order, uint32_t *tr_price,
+                          uint64_t *tr_vol)
 {
     if (d->L < 1 || d->L > 1024) return -1;
+    if ((d->flags & 0xFFu) > ORC_MODEL_MID) return -1;
+    if ((d->flags & 0xFFu) == ORC_MODEL_LAST && (d->flags >> 16) != 0) return -1;
+    if ((d->flags & 0xFF00u) != 0) return -1;
     /* Books are 32-bit: every quantity ever added must fit. */
     if (((uint64_t)st->steps_done + S) * (uint64_t)d->A * (uint64_t)d->Q >= (1ull << 32)) return -2;
     double *lnp = (double *)malloc(sizeof(double) * d->L);
     build_log_prices(d->L, lnp);
-    for (uint32_t i = 0; i < S; ++i)
+    for (uint32_t i = 0; i < S; ++i) {
+        uint64_t vol_before = st->sum_vol;
         orc_market_step(d, m, seed, st, book, book + d->L, lnp, agent_order);
+        if (tr_price) tr_price[i] = st->last;
+        if (tr_vol) tr_vol[i] = st->sum_vol - vol_before;
+    }
     free(lnp);
     return 0;
+}
+
+int orc_market_run(const orc_market *d, uint32_t m, uint64_t seed, uint32_t S, orc_state *st,
+                   uint32_t *book, const uint32_t *agent_order)
+{
+    return orc_market_run_traced(d, m, seed, S, st, book, agent_order, NULL, NULL);
 }
 
 /* ---------------------------------------------------------------------------------------
@@ -278,6 +363,9 @@ typedef struct {
     uint64_t seed;
     uint32_t S;
     uint32_t n;
+    uint32_t *tr_price; /* optional traces, row i at i * tr_ld */
+    uint64_t *tr_vol;
+    uint64_t tr_ld;
     uint32_t next; /* guarded by lock */
     int status;
     pthread_mutex_t lock;
@@ -291,8 +379,10 @@ static void *orc_worker(void *arg)
         uint32_t i = job->next++;
         pthread_mutex_unlock(&job->lock);
         if (i >= job->n) break;
-        int rc = orc_market_run(&job->descs[i], job->ids[i], job->seed, job->S, &job->states[i],
-                                job->book + job->book_off[i], NULL);
+        int rc = orc_market_run_traced(&job->descs[i], job->ids[i], job->seed, job->S, &job->states[i],
+                                       job->book + job->book_off[i], NULL,
+                                       job->tr_price ? job->tr_price + (size_t)i * job->tr_ld : NULL,
+                                       job->tr_vol ? job->tr_vol + (size_t)i * job->tr_ld : NULL);
         if (rc != 0) {
             pthread_mutex_lock(&job->lock);
             job->status = rc;
@@ -302,12 +392,14 @@ static void *orc_worker(void *arg)
     return NULL;
 }
 
-int orc_run(const orc_market *descs, const uint32_t *ids, const uint64_t *book_off, uint32_t n,
-            uint64_t seed, uint32_t S, orc_state *states, uint32_t *book, int nthreads)
+int orc_run_traced(const orc_market *descs, const uint32_t *ids, const uint64_t *book_off, uint32_t n,
+                   uint64_t seed, uint32_t S, orc_state *states, uint32_t *book, int nthreads,
+                   uint32_t *tr_price, uint64_t *tr_vol, uint64_t tr_ld)
 {
     orc_job job;
     job.descs = descs; job.ids = ids; job.book_off = book_off; job.book = book;
     job.states = states; job.seed = seed; job.S = S; job.n = n; job.next = 0; job.status = 0;
+    job.tr_price = tr_price; job.tr_vol = tr_vol; job.tr_ld = tr_ld;
     pthread_mutex_init(&job.lock, NULL);
     if (nthreads < 1) nthreads = 1;
     if ((uint32_t)nthreads > n) nthreads = (int)(n ? n : 1);
@@ -317,6 +409,12 @@ int orc_run(const orc_market *descs, const uint32_t *ids, const uint64_t *book_o
     free(th);
     pthread_mutex_destroy(&job.lock);
     return job.status;
+}
+
+int orc_run(const orc_market *descs, const uint32_t *ids, const uint64_t *book_off, uint32_t n,
+            uint64_t seed, uint32_t S, orc_state *states, uint32_t *book, int nthreads)
+{
+    return orc_run_traced(descs, ids, book_off, n, seed, S, states, book, nthreads, NULL, NULL, 0);
 }
 
 /* Clearing of many independent books of one size (used by the exhaustive pins). */
@@ -338,6 +436,16 @@ void orc_orders(const orc_market *d, uint32_t m, uint64_t seed, uint32_t s, uint
 {
     for (uint32_t a = 0; a < d->A; ++a)
         orc_agent_order(d, m, seed, a, s, last, prev, &side[a], &tick[a], &qty[a]);
+}
+
+/* Mid-price-model orders of agents [0, A) at one step, given mid and the previous mid as
+ * half-tick integers (2 mid, 2 mid_prev). */
+void orc_orders_mid(const orc_market *d, uint32_t m, uint64_t seed, uint32_t s, uint32_t mid2,
+                    uint32_t mid2_prev, uint32_t *side, uint32_t *tick, uint32_t *qty)
+{
+    for (uint32_t a = 0; a < d->A; ++a)
+        orc_agent_order_mid(d, m, seed, a, s, 0.5 * (double)mid2, 0.5 * (double)mid2_prev,
+                            &side[a], &tick[a], &qty[a]);
 }
 
 uint32_t orc_state_size(void) { return (uint32_t)sizeof(orc_state); }

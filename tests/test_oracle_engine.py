@@ -116,8 +116,14 @@ def test_stats_hand_case(orc):
 def _python_step(orc, d, m, seed, st, bid, ask):
     """One step assembled from the oracle's pieces, checking every clearing invariant."""
     L = int(d["L"][0])
-    side, tick, qty = orc.orders(d, m, seed, int(st["steps_done"][0]), int(st["last"][0]),
-                                 int(st["prev"][0]))
+    s = int(st["steps_done"][0])
+    if int(d["flags"][0]) & 0xFF == orc.MODEL_MID:
+        hb, la = np.nonzero(bid)[0], np.nonzero(ask)[0]
+        ref2 = int(hb.max() + la.min()) if len(hb) and len(la) else 2 * int(st["last"][0])
+        side, tick, qty = orc.orders_mid(d, m, seed, s, ref2, int(st["ref2"][0]))
+    else:
+        ref2 = 2 * int(st["last"][0])
+        side, tick, qty = orc.orders(d, m, seed, s, int(st["last"][0]), int(st["prev"][0]))
     b = bid.astype(np.int64).copy()
     a = ask.astype(np.int64).copy()
     np.add.at(b, tick[side == orc.BUY], qty[side == orc.BUY])
@@ -134,6 +140,7 @@ def _python_step(orc, d, m, seed, st, bid, ask):
     if len(hb) and len(la):
         assert hb.max() < la.min()
     orc.update_stats(nb, na, p, v, orc.log_prices(L), st)
+    st["ref2"] = ref2
     return nb, na
 
 
@@ -208,3 +215,116 @@ def test_paper_scale_sanity(orc):
     mean_px = st["sum_px"].sum() / st["n_trade"].sum()
     assert 44 < mean_px < 84
     assert st["n_trade"].min() > 150
+
+
+def test_trace_records_each_step(orc):
+    """The traced run records, per step, the reference tick after the step and the volume
+    executed in it: it equals a step-by-step assembly, and the series reproduce the running
+    statistics (trades, volume, price sum, log-return sums in step order) exactly."""
+    descs = np.concatenate([orc.market(32, 40, 4, 7, n_noise=20, n_mom=10, h=1),
+                            orc.market(64, 128, 8, 10), orc.market(5, 9, 1, 3, n_noise=0, n_mom=9)])
+    S, seed = 60, 9
+    st, bk, pr, vo = orc.run(descs, seed, S, trace=True)
+    st0, bk0 = orc.run(descs, seed, S)
+    assert st.tobytes() == st0.tobytes() and np.array_equal(bk, bk0)
+    L0 = int(descs["L"][0])
+    s = orc.initial_state(descs[:1])
+    bid, ask = np.zeros(L0, np.uint32), np.zeros(L0, np.uint32)
+    for t in range(S):
+        v_before = int(s["sum_vol"][0])
+        bid, ask = _python_step(orc, descs[:1], 0, seed, s, bid, ask)
+        assert pr[0, t] == s["last"][0] and vo[0, t] == int(s["sum_vol"][0]) - v_before
+    for i in range(len(descs)):
+        L = int(descs["L"][i])
+        assert vo[i].sum() == st["sum_vol"][i]
+        assert (vo[i] > 0).sum() == st["n_trade"][i]
+        assert pr[i][vo[i] > 0].astype(np.uint64).sum() == st["sum_px"][i]
+        ref = np.concatenate([[L // 2], pr[i][:-1]]).astype(np.int64)
+        assert np.all(pr[i][vo[i] == 0] == ref[vo[i] == 0])  # no trade: price unchanged
+        lnp = orc.log_prices(L)
+        acc, acc2 = 0.0, 0.0
+        for x in lnp[pr[i]] - lnp[ref]:
+            acc, acc2 = acc + x, acc2 + x * x
+        assert acc == st["sum_r"][i] and acc2 == st["sum_r2"][i]
+    # series of a split run concatenate to the series of the whole run
+    st1, bk1, p1, v1 = orc.run(descs, seed, 25, trace=True)
+    _, _, p2, v2 = orc.run(descs, seed, S - 25, states=st1, book=bk1, trace=True)
+    assert np.array_equal(np.hstack([p1, p2]), pr) and np.array_equal(np.hstack([v1, v2]), vo)
+
+
+def _exact_mid_order(orc, d, m, seed, a, s, mid2, mid2_prev):
+    """The paper's mid-price agent rules (section III-C) evaluated in exact rationals."""
+    from fractions import Fraction as F
+    L, K, Q = int(d["L"][0]), int(d["K"][0]), int(d["Q"][0])
+    nn, nm, h = int(d["n_noise"][0]), int(d["n_mom"][0]), int(d["h"][0])
+    p_mkt = F(int(d["flags"][0]) >> 16, 65536)
+    w = orc.philox([s, a, m, 0], [seed & 0xFFFFFFFF, seed >> 32])
+    u = [F(int(x), 2**32) for x in w]
+    mid, mid_prev = F(mid2, 2), F(mid2_prev, 2)
+    coin = orc.BUY if u[0] < F(1, 2) else orc.SELL
+    rnd = lambda x: math.floor(x + F(1, 2))
+    mkt = u[3] < p_mkt
+    if a < nn:
+        side, price = coin, rnd(mid + K * (2 * u[1] - 1))
+    elif a < nn + nm:
+        side = orc.BUY if mid > mid_prev else orc.SELL if mid < mid_prev else coin
+        price = rnd(mid + (1 if side == orc.BUY else -1))
+    else:
+        side = orc.BUY if (a + s) % 2 == 0 else orc.SELL
+        price = rnd(mid - h if side == orc.BUY else mid + h)
+        mkt = False
+    if mkt:
+        price = L - 1 if side == orc.BUY else 0
+    return side, min(max(price, 0), L - 1), 1 + (int(w[2]) * Q >> 32)
+
+
+@pytest.mark.parametrize("L,K,h,p16,mid2,mid2_prev", [
+    (128, 8, 2, 0, 129, 129), (128, 8, 2, 6554, 128, 130), (128, 8, 2, 6554, 131, 127),
+    (10, 9, 4, 32768, 1, 0), (10, 9, 4, 65535, 17, 18), (64, 1, 1, 0, 0, 0),
+    (1024, 1023, 30, 1000, 2045, 3)])
+def test_mid_model_orders_exact(orc, L, K, h, p16, mid2, mid2_prev):
+    d = orc.market(L, 300, K, 17, n_noise=150, n_mom=90, h=h, flags=orc.model_flags(orc.MODEL_MID, p16))
+    for s in (0, 7):
+        side, tick, qty = orc.orders_mid(d, 5, 1234567890123, s, mid2, mid2_prev)
+        for a in range(300):
+            assert (side[a], tick[a], qty[a]) == _exact_mid_order(orc, d, 5, 1234567890123, a, s,
+                                                                  mid2, mid2_prev), (a, s)
+
+
+def test_mid_model_hand_values(orc):
+    """Best bid 3, best ask 6 -> mid 4.5: makers with h = 2 post round(2.5) = 3 and round(6.5)
+    = 7; momentum after a rise buys at round(5.5) = 6, after a fall sells at round(3.5) = 4."""
+    d = orc.market(10, 4, 2, 1, n_noise=0, n_mom=2, h=2, flags=orc.model_flags(orc.MODEL_MID))
+    side, tick, _ = orc.orders_mid(d, 0, 0, 0, 9, 8)  # mid rose from 4 to 4.5
+    assert list(side[:2]) == [orc.BUY, orc.BUY] and list(tick[:2]) == [6, 6]
+    assert (side[2], tick[2]) == (orc.BUY, 3) and (side[3], tick[3]) == (orc.SELL, 7)
+    side, tick, _ = orc.orders_mid(d, 0, 0, 0, 9, 10)  # mid fell from 5 to 4.5
+    assert list(side[:2]) == [orc.SELL, orc.SELL] and list(tick[:2]) == [4, 4]
+
+
+@pytest.mark.parametrize("cfg", [(64, 128, 8, 10, 60, 40, 2, 6554), (32, 40, 4, 7, 20, 10, 1, 0),
+                                 (8, 33, 3, 5, 11, 11, 2, 30000)])
+def test_mid_model_assembly_and_invariants(orc, cfg):
+    """Mid-price model: the oracle's steps equal an assembly from its pieces, with the
+    reference read from the resting book at the start of each step; every clearing
+    invariant holds."""
+    L, A, K, Q, nn, nm, h, p16 = cfg
+    d = orc.market(L, A, K, Q, n_noise=nn, n_mom=nm, h=h, flags=orc.model_flags(orc.MODEL_MID, p16))
+    m, seed, S = 2, 99, 50
+    st = orc.initial_state(d)
+    bid, ask = np.zeros(L, np.uint32), np.zeros(L, np.uint32)
+    for _ in range(S):
+        bid, ask = _python_step(orc, d, m, seed, st, bid, ask)
+    st2, bk2 = orc.market_run(d, m, seed, S)
+    assert st2.tobytes() == st.tobytes()
+    assert bk2.tolist() == bid.tolist() + ask.tolist()
+    st3, bk3 = orc.market_run(d, m, seed, 21)
+    st3, bk3 = orc.market_run(d, m, seed, S - 21, state=st3, book=bk3)
+    assert st3.tobytes() == st2.tobytes() and np.array_equal(bk3, bk2)
+
+
+def test_model_flags_validated(orc):
+    with pytest.raises(ValueError):
+        orc.market_run(orc.market(16, 8, 2, 3, flags=orc.model_flags(orc.MODEL_LAST, 5)), 0, 0, 1)
+    with pytest.raises(ValueError):
+        orc.market_run(orc.market(16, 8, 2, 3, flags=2), 0, 0, 1)
