@@ -28,6 +28,15 @@
  *                                      tick = ref + 1 for BUY, ref - 1 for SELL
  *     MAKER    (the rest):             BUY iff (a + s) is even; tick = ref - h (BUY) or ref + h (SELL)
  *   every tick is clamped to [0, L-1]; quantity = 1 + floor(w2 * Q / 2^32).
+ * That is the last-tick model (CAE_MODEL_LAST).  The mid-price model (CAE_MODEL_MID) follows
+ * the paper's own rules (section III-C, "State Retrieval", "Agent Strategy Classes"): at the
+ * start of each step the reference is mid = (bb + ba) / 2 of the resting book when both sides
+ * are quoted, else the last clearing tick; round(x) = floor(x + 1/2); u_i = w_i / 2^32:
+ *     NOISE:    side BUY iff w0 < 2^31; tick = round(mid + K (2 u1 - 1)), eta uniform on [-K, K)
+ *     MOMENTUM: side = sign(mid - mid of the previous step) (w0 rule if 0); tick = round(mid +- 1)
+ *     MAKER:    BUY iff (a + s) is even; tick = round(mid - h) (BUY) or round(mid + h) (SELL)
+ *   and a NOISE or MOMENTUM order is marketable when u3 < P_mkt: tick L-1 for a BUY, 0 for a
+ *   SELL.  Ticks are clamped and quantities drawn as above.
  * Clearing: the combined book (resting + new) clears at p*, the lowest tick of maximal
  * V(p) = min(D(p), S(p)); bids fill from the highest tick down and asks from the lowest tick
  * up until V* shares each.  If V* = 0 nothing trades and the price is unchanged.
@@ -55,9 +64,18 @@ extern "C" {
 #define CAE_EHIP (-4)      /* the HIP runtime reported an error (message has its text)      */
 #define CAE_ESTATE (-5)    /* the handle is not in a state that allows the call             */
 
+/* Agent models (bits 0-7 of cae_market.flags) and the marketable-order probability P_mkt of
+ * the mid-price model (bits 16-31, in units of 2^-16: an order is marketable iff
+ * w3 < (flags >> 16) << 16). */
+#define CAE_MODEL_LAST 0u
+#define CAE_MODEL_MID 1u
+#define CAE_MODEL_MASK 0xFFu
+#define CAE_PMKT_SHIFT 16
+
 /* One market (32 bytes).  Constraints checked by cae_sizes and cae_create:
- *   1 <= L <= 1024, A >= 1, K <= 2^30, Q >= 1, A * Q < 2^32, n_noise + n_mom <= A,
- *   maker_half_spread < L, flags == 0. */
+ *   1 <= L <= 1024, A >= 1, K <= 2^30 (K < 2^20 in the mid-price model), Q >= 1,
+ *   A * Q < 2^32, n_noise + n_mom <= A, maker_half_spread < L; flags: model LAST or MID,
+ *   bits 8-15 zero, P_mkt zero in the last-tick model. */
 typedef struct cae_market {
     uint32_t L;                 /* ticks on the price grid                                */
     uint32_t A;                 /* agents                                                 */
@@ -66,10 +84,10 @@ typedef struct cae_market {
     uint32_t n_noise;           /* agents [0, n_noise) are NOISE                          */
     uint32_t n_mom;             /* agents [n_noise, n_noise + n_mom) MOMENTUM; rest MAKER */
     uint32_t maker_half_spread; /* h, in ticks                                            */
-    uint32_t flags;             /* must be 0                                              */
+    uint32_t flags;             /* agent model and P_mkt (CAE_MODEL_*, CAE_PMKT_SHIFT)    */
 } cae_market;
 
-/* Per-market state and statistics (72 bytes, this exact layout in device memory). */
+/* Per-market state and statistics (80 bytes, this exact layout in device memory). */
 typedef struct cae_state {
     uint32_t last;       /* last clearing tick                                 */
     uint32_t prev;       /* reference before the last step                     */
@@ -81,6 +99,10 @@ typedef struct cae_state {
     uint64_t n_spread;
     double sum_r;
     double sum_r2;
+    uint32_t ref2;       /* twice the reference price of the latest step (the last tick, or
+                            the mid-price), the mid-price model's momentum memory; opening
+                            value 2 floor(L / 2) */
+    uint32_t reserved;   /* 0                                                  */
 } cae_state;
 
 /* Device memory an ensemble needs (from cae_sizes). */
@@ -159,6 +181,19 @@ int cae_create(const cae_market *desc, uint32_t M, uint64_t seed, const uint32_t
  * (steps_done + S) * A * Q >= 2^32 (a 32-bit book could then overflow).  S == 0 is a
  * no-op.  Errors: CAE_EINVAL, CAE_EOVERFLOW, CAE_EHIP. */
 int cae_step(cae_ensemble *e, uint32_t S);
+
+/* cae_step that also records each market's per-step price and volume series, the raw data of
+ * the paper's market-dynamics experiments (section IV-J: volatility, return kurtosis, volume
+ * and return autocorrelations against the agent mix).  For market m (descriptor order) and
+ * step i of this call (0 <= i < S):
+ *   dev_price[m * ld + i]  = the reference tick `last` after step i (unchanged when nothing
+ *                            traded), in [0, L);
+ *   dev_volume[m * ld + i] = the volume V* executed in step i (0: no trade).
+ * Both are caller-owned device arrays of at least M * ld words; either may be NULL (then that
+ * series is not written).  ld >= S, so successive calls can fill columns of one larger array.
+ * Same schedule, results and errors as cae_step, plus CAE_EINVAL when ld < S. */
+int cae_step_traced(cae_ensemble *e, uint32_t S, uint32_t *dev_price, uint32_t *dev_volume,
+                    uint64_t ld);
 
 /* Copy the packed books (layout of cae_buffers.book) to host_book[n_words] after the
  * stream's pending work; returns when the copy is complete.  CAE_ENOSPACE if n_words is

@@ -23,7 +23,12 @@ class State(C.Structure):
     _fields_ = [("last", C.c_uint32), ("prev", C.c_uint32), ("steps_done", C.c_uint64),
                 ("n_trade", C.c_uint64), ("sum_vol", C.c_uint64), ("sum_px", C.c_uint64),
                 ("sum_spread", C.c_uint64), ("n_spread", C.c_uint64),
-                ("sum_r", C.c_double), ("sum_r2", C.c_double)]
+                ("sum_r", C.c_double), ("sum_r2", C.c_double),
+                ("ref2", C.c_uint32), ("reserved", C.c_uint32)]
+
+
+# Agent models (descriptor flags bits 0-7) and the position of P_mkt (bits 16-31).
+MODEL_LAST, MODEL_MID, PMKT_SHIFT = 0, 1, 16
 
 
 class Sizes(C.Structure):
@@ -60,7 +65,7 @@ class CaeError(RuntimeError):
 
 
 EXPORTS = ["cae_strerror", "cae_last_error", "cae_device_info", "cae_sizes", "cae_create",
-           "cae_step", "cae_step_naive", "cae_read_books", "cae_read_state", "cae_write_state", "cae_get_tuning",
+           "cae_step", "cae_step_naive", "cae_step_traced", "cae_read_books", "cae_read_state", "cae_write_state", "cae_get_tuning",
            "cae_last_step_ms", "cae_destroy", "cae_clear", "cae_mlp_sizes",
            "cae_mlp_refresh_weights", "cae_mlp_forward", "cae_mlp_backward", "cae_mlp_adam",
            "cae_mlp_loss_grad"]
@@ -85,6 +90,7 @@ def lib():
     L.cae_create.argtypes = [P, u32, u64, P, P, P, P, P]
     L.cae_step.argtypes = [P, u32]
     L.cae_step_naive.argtypes = [P, u32]
+    L.cae_step_traced.argtypes = [P, u32, P, P, u64]
     L.cae_read_books.argtypes = [P, P, u64]
     L.cae_read_state.argtypes = [P, P, u32]
     L.cae_write_state.argtypes = [P, P, u32, P, u64]

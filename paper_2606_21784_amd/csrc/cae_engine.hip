@@ -46,7 +46,7 @@ struct DevMarket {
     uint32_t n_noise, n_mom, h, tpl;  // tpl: ticks per lane of the clearing wave (power of 2)
     uint64_t book_off;                // word offset of bid[0]; ask[0] is at book_off + L
     uint32_t id;                      // market index in the generator counter
-    uint32_t pad;
+    uint32_t flags;                   // agent model (bits 0-7) and P_mkt (bits 16-31)
 };
 static_assert(sizeof(DevMarket) == 48, "DevMarket layout");
 
@@ -68,11 +68,23 @@ struct EngineArgs {
     uint32_t *book;
     cae_state *state;
     const double *lnT;  // lnT[n] = ln(n), n in [0, 2048]
+    uint32_t *tr_price;  // optional per-step series, row m at m * tr_ld: last tick after step i
+    uint32_t *tr_vol;    // and the volume executed in step i
+    uint64_t tr_ld;
     uint32_t n_items;
     uint32_t n_claimers;
     uint32_t S;
     uint32_t k0, k1;
 };
+
+// Records step i of market m in the optional series (one lane per market-step).
+__device__ __forceinline__ void trace_step(const EngineArgs &args, uint32_t m, uint32_t i, uint32_t last,
+                                           uint32_t v)
+{
+    const uint64_t at = (uint64_t)m * args.tr_ld + i;
+    if (args.tr_price != nullptr) args.tr_price[at] = last;
+    if (args.tr_vol != nullptr) args.tr_vol[at] = v;
+}
 
 constexpr uint32_t kM0 = 0xD2511F53u;
 constexpr uint32_t kM1 = 0xCD9E8D57u;
@@ -122,6 +134,13 @@ struct PhiloxStep {
 
     __device__ __forceinline__ void words(uint32_t a, uint32_t &w0, uint32_t &w1, uint32_t &w2) const
     {
+        uint32_t w3;
+        words4(a, w0, w1, w2, w3);
+    }
+
+    __device__ __forceinline__ void words4(uint32_t a, uint32_t &w0, uint32_t &w1, uint32_t &w2,
+                                           uint32_t &w3) const
+    {
         uint32_t h, l;
         mulhilo(kM0, ua ^ a, h, l);
         const uint32_t y2 = h ^ ux3k, y3 = l;
@@ -140,6 +159,7 @@ struct PhiloxStep {
         w0 = c0;
         w1 = c1;
         w2 = c2;
+        w3 = c3;
     }
 };
 
@@ -150,17 +170,6 @@ template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ uint32_t dpp(uint32_t x)
 {
     return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROW_MASK, 0xf, false);
-}
-
-__device__ __forceinline__ uint32_t wave_scan_add(uint32_t x)  // inclusive
-{
-    x += dpp<0x111, 0xf>(x);
-    x += dpp<0x112, 0xf>(x);
-    x += dpp<0x114, 0xf>(x);
-    x += dpp<0x118, 0xf>(x);
-    x += dpp<0x142, 0xa>(x);
-    x += dpp<0x143, 0xc>(x);
-    return x;
 }
 
 // Two inclusive scans interleaved, so each DPP read follows an unrelated write (no wait states).
@@ -349,77 +358,155 @@ __device__ __forceinline__ ClearOut clear_dispatch(uint32_t *bk, uint32_t tpl, u
     return clear_wave<1>(bk, lane);
 }
 
-// The order rules of section III-C (this library's readings), shared by the persistent engine
-// and the naive one-thread-per-market engine so both produce identical books.
-struct OrderCtx {
-    int base;          // last - K
-    uint32_t span;     // 2K + 1
-    uint32_t Q;
-    int top;           // L - 1
-    uint32_t n_noise, mom_end;
-    int h;
-    uint32_t last, prev, s;
+// The references the agents of a market read at the start of a step.
+struct Refs {
+    uint32_t last, prev;   // last clearing tick, and the one before the previous step
+    uint32_t mid2, mid2p;  // mid-price model: 2 mid of this step and of the previous step
 };
 
-__device__ __forceinline__ OrderCtx order_ctx(const DevMarket &d, uint32_t s, uint32_t last, uint32_t prev)
+// The order rules of section III-C, shared by the persistent engine and the naive
+// one-thread-per-market engine so both produce identical books.  Last-tick model: reference =
+// last, momentum follows sign(last - prev).  Mid-price model: reference = mid (half-ticks,
+// round(x) = floor(x + 1/2)), momentum follows sign(mid - mid of the previous step), NOISE and
+// MOMENTUM orders are marketable with probability P_mkt.  Every value here is uniform.
+struct OrderCtx {
+    int base;           // last-tick NOISE: last - K
+    uint32_t span;      // 2K + 1
+    uint64_t nbase;     // mid-price NOISE: (2 mid + 1) 2^31 - K 2^32 (two's complement)
+    uint32_t twoK;
+    uint32_t tmkt;      // marketable iff w3 < tmkt (0 in the last-tick model)
+    uint32_t Q;
+    int top;            // L - 1
+    uint32_t n_noise, mom_end, s;
+    uint32_t mom_dir;   // 0 up (buy), 1 down (sell), 2 unchanged (coin)
+    int mom_bid, mom_ask, mk_bid, mk_ask;  // unclamped ticks
+    bool mid;
+};
+
+__device__ __forceinline__ OrderCtx order_ctx(const DevMarket &d, uint32_t s, const Refs &r)
 {
     OrderCtx o;
-    o.base = (int)last - (int)d.K;
+    o.mid = (d.flags & CAE_MODEL_MASK) == CAE_MODEL_MID;
     o.span = 2u * d.K + 1u;
+    o.twoK = 2u * d.K;
     o.Q = d.Q;
     o.top = (int)d.L - 1;
     o.n_noise = d.n_noise;
     o.mom_end = d.n_noise + d.n_mom;
-    o.h = (int)d.h;
-    o.last = last;
-    o.prev = prev;
     o.s = s;
+    const int h = (int)d.h;
+    if (o.mid) {
+        const int m2 = (int)r.mid2;
+        o.base = 0;
+        o.nbase = ((uint64_t)(r.mid2 + 1u) << 31) - ((uint64_t)d.K << 32);
+        o.tmkt = (d.flags >> CAE_PMKT_SHIFT) << CAE_PMKT_SHIFT;
+        o.mom_dir = r.mid2 > r.mid2p ? 0u : (r.mid2 < r.mid2p ? 1u : 2u);
+        o.mom_bid = (m2 + 3) >> 1;           // round(mid + 1)
+        o.mom_ask = (m2 - 1) >> 1;           // round(mid - 1)
+        o.mk_bid = (m2 - 2 * h + 1) >> 1;    // round(mid - h)
+        o.mk_ask = (m2 + 2 * h + 1) >> 1;    // round(mid + h)
+    } else {
+        const int l = (int)r.last;
+        o.base = l - (int)d.K;
+        o.nbase = 0;
+        o.tmkt = 0;
+        o.mom_dir = r.last > r.prev ? 0u : (r.last < r.prev ? 1u : 2u);
+        o.mom_bid = l + 1;
+        o.mom_ask = l - 1;
+        o.mk_bid = l - h;
+        o.mk_ask = l + h;
+    }
     return o;
 }
 
 __device__ __forceinline__ uint32_t order_qty(const OrderCtx &o, uint32_t w2) { return 1u + __umulhi(w2, o.Q); }
 
-// NOISE agent: fair coin for the side (w0), uniform offset in {-K..K} (w1); book word 2*tick+side.
+// Last-tick NOISE agent: fair coin for the side (w0), uniform offset in {-K..K} (w1); book
+// word 2*tick+side.
 __device__ __forceinline__ uint32_t noise_word(const OrderCtx &o, uint32_t w0, uint32_t w1)
 {
     const int tick = min(max(o.base + (int)__umulhi(w1, o.span), 0), o.top);
     return 2u * (uint32_t)tick + (w0 >> 31);
 }
 
-// MOMENTUM (a < mom_end) or MAKER agent a.
-__device__ __forceinline__ uint32_t other_word(const OrderCtx &o, uint32_t a, uint32_t w0)
+// Mid-price NOISE agent: tick = floor(mid + K (2 w1 / 2^32 - 1) + 1/2), the high word of a
+// 64-bit fixed-point sum with 32 fraction bits; marketable when w3 < tmkt.
+__device__ __forceinline__ uint32_t mid_noise_word(const OrderCtx &o, uint32_t w0, uint32_t w1, uint32_t w3)
+{
+    const uint32_t sell = w0 >> 31;
+    int tick = (int)(uint32_t)((o.nbase + (uint64_t)o.twoK * (uint64_t)w1) >> 32);
+    if (w3 < o.tmkt) tick = sell ? 0 : o.top;
+    tick = min(max(tick, 0), o.top);
+    return 2u * (uint32_t)tick + sell;
+}
+
+// MOMENTUM (a < mom_end) or MAKER agent a, either model.
+__device__ __forceinline__ uint32_t other_word(const OrderCtx &o, uint32_t a, uint32_t w0, uint32_t w3)
 {
     uint32_t sell;
     int tick;
-    if (a < o.mom_end) {  // MOMENTUM: follow the last price change, coin when unchanged
-        sell = o.last > o.prev ? 0u : (o.last < o.prev ? 1u : (w0 >> 31));
-        tick = (int)o.last + (sell ? -1 : 1);
-    } else {  // MAKER: buy when a + s is even, h ticks from the reference
+    if (a < o.mom_end) {
+        sell = o.mom_dir == 2u ? (w0 >> 31) : o.mom_dir;
+        tick = sell ? o.mom_ask : o.mom_bid;
+        if (w3 < o.tmkt) tick = sell ? 0 : o.top;
+    } else {  // MAKER: buy when a + s is even
         sell = (a ^ o.s) & 1u;
-        tick = (int)o.last + (sell ? o.h : -o.h);
+        tick = sell ? o.mk_ask : o.mk_bid;
     }
     tick = min(max(tick, 0), o.top);
     return 2u * (uint32_t)tick + sell;
 }
 
 // Every order of one market-step, added into the LDS book (interleaved pairs: word 2*tick+side).
-__device__ __forceinline__ void gen_orders(const DevMarket &d, uint32_t m, uint32_t s,
-                                           uint32_t last, uint32_t prev, uint32_t key0,
-                                           uint32_t key1, uint32_t t, uint32_t nthr, uint32_t *bk)
+__device__ __forceinline__ void gen_orders(const DevMarket &d, uint32_t m, uint32_t s, const Refs &r,
+                                           uint32_t key0, uint32_t key1, uint32_t t, uint32_t nthr,
+                                           uint32_t *bk)
 {
     const PhiloxStep ph(s, m, key0, key1);
-    const OrderCtx o = order_ctx(d, s, last, prev);
+    const OrderCtx o = order_ctx(d, s, r);
     uint32_t a = t;
-    for (; a < d.n_noise; a += nthr) {
-        uint32_t w0, w1, w2;
-        ph.words(a, w0, w1, w2);
-        atomicAdd(&bk[noise_word(o, w0, w1)], order_qty(o, w2));
+    if (o.mid) {
+        for (; a < d.n_noise; a += nthr) {
+            uint32_t w0, w1, w2, w3;
+            ph.words4(a, w0, w1, w2, w3);
+            atomicAdd(&bk[mid_noise_word(o, w0, w1, w3)], order_qty(o, w2));
+        }
+    } else {
+        for (; a < d.n_noise; a += nthr) {
+            uint32_t w0, w1, w2;
+            ph.words(a, w0, w1, w2);
+            atomicAdd(&bk[noise_word(o, w0, w1)], order_qty(o, w2));
+        }
     }
     for (; a < d.A; a += nthr) {
-        uint32_t w0, w1, w2;
-        ph.words(a, w0, w1, w2);
-        atomicAdd(&bk[other_word(o, a, w0)], order_qty(o, w2));
+        uint32_t w0, w1, w2, w3;
+        ph.words4(a, w0, w1, w2, w3);
+        atomicAdd(&bk[other_word(o, a, w0, w3)], order_qty(o, w2));
     }
+}
+
+// Best bid / best ask (kNone when a side is empty) of an LDS book, by one wave: the reference
+// of the mid-price model at the start of a call (later steps take them from the clearing).
+__device__ __forceinline__ void book_ends(const uint32_t *bk, uint32_t tpl, uint32_t lane, uint32_t &bb,
+                                          uint32_t &ba)
+{
+    uint32_t hb = kNone, la = kNone;
+    for (uint32_t j = 0; j < tpl; ++j) {
+        const uint32_t q = lane * tpl + j;
+        const uint2 v = reinterpret_cast<const uint2 *>(bk)[q];
+        if (v.x != 0) hb = q;
+        if (v.y != 0 && la == kNone) la = q;
+    }
+    const uint64_t mb = ballot(hb != kNone);
+    const uint64_t ma = ballot(la != kNone);
+    bb = mb ? readlane(hb, 63u - (uint32_t)__builtin_clzll(mb)) : kNone;
+    ba = ma ? readlane(la, (uint32_t)__builtin_ctzll(ma)) : kNone;
+}
+
+// The reference of the step after one that left best bid bb and best ask ba and price last.
+__device__ __forceinline__ uint32_t next_mid2(bool mid, uint32_t bb, uint32_t ba, uint32_t last)
+{
+    return (mid && bb != kNone && ba != kNone) ? bb + ba : 2u * last;
 }
 
 // One market (or an idle slot of a lock-step item) for all S steps.  MULTI: the market spans
@@ -437,7 +524,7 @@ __device__ __forceinline__ void run_market(const EngineArgs &args, const Item &i
 
     uint32_t m = 0;
     DevMarket d{};
-    uint32_t last = 0, prev = 0;
+    uint32_t last = 0, prev = 0, mid2 = 0, mid2p = 0;
     uint64_t steps0 = 0, n_trade = 0, sum_vol = 0, sum_px = 0, sum_spread = 0, n_spread = 0;
     double sum_r = 0.0, sum_r2 = 0.0;
     if (active) {
@@ -454,6 +541,7 @@ __device__ __forceinline__ void run_market(const EngineArgs &args, const Item &i
         n_spread = st->n_spread;
         sum_r = st->sum_r;
         sum_r2 = st->sum_r2;
+        mid2p = st->ref2;
         const uint32_t *gb = args.book + d.book_off;
         const uint32_t padded = 64u * d.tpl;
         for (uint32_t q = t; q < padded; q += nthr) {
@@ -467,11 +555,18 @@ __device__ __forceinline__ void run_market(const EngineArgs &args, const Item &i
     }
     if constexpr (MULTI) __syncthreads();
     else wave_sync();
+    const bool mid = (d.flags & CAE_MODEL_MASK) == CAE_MODEL_MID;
+    mid2 = 2u * last;
+    if (active && mid) {
+        uint32_t bb, ba;
+        book_ends(bk, d.tpl, lane, bb, ba);
+        mid2 = next_mid2(true, bb, ba, last);
+    }
 
     const double *lnT = args.lnT + d.L;  // ln(L + tick)
     for (uint32_t i = 0; i < args.S; ++i) {
         const uint32_t s = (uint32_t)steps0 + i;
-        if (active) gen_orders(d, d.id, s, last, prev, args.k0, args.k1, t, nthr, bk);
+        if (active) gen_orders(d, d.id, s, Refs{last, prev, mid2, mid2p}, args.k0, args.k1, t, nthr, bk);
         if constexpr (MULTI) __syncthreads();
         else wave_sync();
         ClearOut co;
@@ -502,9 +597,12 @@ __device__ __forceinline__ void run_market(const EngineArgs &args, const Item &i
                 sum_spread += (uint64_t)(co.ba - co.bb);
                 n_spread += 1;
             }
+            mid2p = mid2;
+            mid2 = next_mid2(mid, co.bb, co.ba, last);
             const double r = lnT[last] - lnT[prev];
             sum_r = sum_r + r;
             sum_r2 = sum_r2 + r * r;
+            if (t == 0) trace_step(args, m, i, last, co.v);
         }
     }
     if (active) {
@@ -526,23 +624,22 @@ __device__ __forceinline__ void run_market(const EngineArgs &args, const Item &i
             st->n_spread = n_spread;
             st->sum_r = sum_r;
             st->sum_r2 = sum_r2;
+            st->ref2 = mid2p;
         }
     }
 }
 
 // Scratch layout of a pipelined market (32-bit words): 0 last, 1 prev, 2-3 steps at item start,
 // 4-5 n_trade, 6-7 sum_vol, 8-9 sum_px, 10-11 sum_spread, 12-13 n_spread, 14-15 sum_r,
-// 16-17 sum_r2.
+// 16-17 sum_r2, 18 ref2 (2 x the previous step's reference), 19 reserved (words 0-19 are the
+// cae_state record), 20 mid2 (2 x the next step's reference).
+constexpr uint32_t kStateWords = sizeof(cae_state) / 4u;
+static_assert(kStateWords == 20 && kStateWords + 1u <= kScr, "pipelined scratch layout");
 __device__ __forceinline__ uint64_t lds_u64(const uint32_t *p)
 {
     const uint2 v = *reinterpret_cast<const uint2 *>(p);
     return ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)v.y) << 32) |
            (uint32_t)__builtin_amdgcn_readfirstlane((int)v.x);
-}
-
-__device__ __forceinline__ uint32_t lds_u32(const uint32_t *p)
-{
-    return (uint32_t)__builtin_amdgcn_readfirstlane((int)*p);
 }
 
 __device__ __forceinline__ void st_u64(uint32_t *p, uint64_t v)
@@ -588,7 +685,25 @@ __device__ __forceinline__ void run_pair(const EngineArgs &args, const Item &ite
                 }
                 reinterpret_cast<uint2 *>(bk)[q] = v;
             }
-            if (tid < 18u) scr[tid] = reinterpret_cast<const uint32_t *>(args.state + m)[tid];
+            if (tid < kStateWords) scr[tid] = reinterpret_cast<const uint32_t *>(args.state + m)[tid];
+        }
+    }
+    __syncthreads();
+    // reference of each market's first step (wave x of the workgroup reads market x's book)
+#pragma unroll
+    for (uint32_t x = 0; x < 2; ++x) {
+        if (x < npair && wave == x % G) {
+            const DevMarket &dm = x ? dB : dA;
+            uint32_t *bk = lds + x * item.stride;
+            uint32_t *scr = bk + item.stride - kScr;
+            const uint32_t last = (uint32_t)__builtin_amdgcn_readfirstlane((int)scr[0]);
+            uint32_t mid2 = 2u * last;
+            if ((dm.flags & CAE_MODEL_MASK) == CAE_MODEL_MID) {
+                uint32_t bb, ba;
+                book_ends(bk, dm.tpl, lane, bb, ba);
+                mid2 = next_mid2(true, bb, ba, last);
+            }
+            if (lane == 0) scr[20] = mid2;
         }
     }
     __syncthreads();
@@ -631,7 +746,13 @@ __device__ __forceinline__ void run_pair(const EngineArgs &args, const Item &ite
                 }
                 const double *lnT = args.lnT + dy.L;
                 const double r = lnT[last] - lnT[last0];
+                if (lane == 0) trace_step(args, Y ? mB : mA, (p - 1u) >> 1, last, co.v);
+                const uint32_t mid2_used = (uint32_t)__builtin_amdgcn_readfirstlane((int)scr[20]);
+                const uint32_t mid2_next =
+                    next_mid2((dy.flags & CAE_MODEL_MASK) == CAE_MODEL_MID, co.bb, co.ba, last);
                 if (lane == 0) {
+                    scr[18] = mid2_used;
+                    scr[20] = mid2_next;
                     scr[0] = last;
                     scr[1] = last0;
                     st_u64(scr + 4, n_trade);
@@ -650,7 +771,13 @@ __device__ __forceinline__ void run_pair(const EngineArgs &args, const Item &ite
             const uint32_t prev = (uint32_t)__builtin_amdgcn_readfirstlane((int)s0.y);
             const uint32_t s = (uint32_t)__builtin_amdgcn_readfirstlane((int)s0.z) + (p >> 1);
             const DevMarket &dx = X ? dB : dA;
-            gen_orders(dx, dx.id, s, last, prev, args.k0, args.k1, (gidx << 6) | lane, (G - 1u) << 6, bk);
+            Refs r{last, prev, 0u, 0u};
+            if ((dx.flags & CAE_MODEL_MASK) == CAE_MODEL_MID) {
+                const uint32_t *scr = bk + item.stride - kScr;
+                r.mid2p = (uint32_t)__builtin_amdgcn_readfirstlane((int)scr[18]);
+                r.mid2 = (uint32_t)__builtin_amdgcn_readfirstlane((int)scr[20]);
+            }
+            gen_orders(dx, dx.id, s, r, args.k0, args.k1, (gidx << 6) | lane, (G - 1u) << 6, bk);
         }
         __syncthreads();
         gidx = gidx == 0u ? G - 1u : gidx - 1u;
@@ -670,7 +797,7 @@ __device__ __forceinline__ void run_pair(const EngineArgs &args, const Item &ite
             }
             if (tid == 0) st_u64(scr + 2, lds_u64(scr + 2) + S);
             __syncthreads();
-            if (tid < 18u) reinterpret_cast<uint32_t *>(args.state + m)[tid] = scr[tid];
+            if (tid < kStateWords) reinterpret_cast<uint32_t *>(args.state + m)[tid] = scr[tid];
         }
     }
 }
@@ -727,14 +854,26 @@ __global__ void __launch_bounds__(64) cae_naive_kernel(const EngineArgs args, ui
     uint32_t *ask = bid + d.L;
     cae_state st = args.state[m];
     const double *lnT = args.lnT + d.L;
+    const bool mid = (d.flags & CAE_MODEL_MASK) == CAE_MODEL_MID;
+    uint32_t mid2p = st.ref2, mid2 = 2u * st.last;
+    if (mid) {
+        int bb = -1, ba = -1;
+        for (int p = (int)d.L - 1; p >= 0 && bb < 0; --p)
+            if (bid[p]) bb = p;
+        for (int p = 0; p < (int)d.L && ba < 0; ++p)
+            if (ask[p]) ba = p;
+        if (bb >= 0 && ba >= 0) mid2 = (uint32_t)(bb + ba);
+    }
     for (uint32_t i = 0; i < args.S; ++i) {
         const uint32_t s = (uint32_t)st.steps_done + i;
         const PhiloxStep ph(s, d.id, args.k0, args.k1);
-        const OrderCtx o = order_ctx(d, s, st.last, st.prev);
+        const OrderCtx o = order_ctx(d, s, Refs{st.last, st.prev, mid2, mid2p});
         for (uint32_t a = 0; a < d.A; ++a) {
-            uint32_t w0, w1, w2;
-            ph.words(a, w0, w1, w2);
-            const uint32_t w = a < d.n_noise ? noise_word(o, w0, w1) : other_word(o, a, w0);
+            uint32_t w0, w1, w2, w3;
+            ph.words4(a, w0, w1, w2, w3);
+            const uint32_t w = a >= d.n_noise ? other_word(o, a, w0, w3)
+                               : mid          ? mid_noise_word(o, w0, w1, w3)
+                                              : noise_word(o, w0, w1);
             const uint32_t q = order_qty(o, w2);
             if (w & 1u) ask[w >> 1] += q;
             else bid[w >> 1] += q;
@@ -788,10 +927,13 @@ __global__ void __launch_bounds__(64) cae_naive_kernel(const EngineArgs args, ui
             st.sum_spread += (uint64_t)(ba - bb);
             st.n_spread += 1;
         }
+        mid2p = mid2;
+        mid2 = next_mid2(mid, bb >= 0 ? (uint32_t)bb : kNone, ba >= 0 ? (uint32_t)ba : kNone, st.last);
         const double r = lnT[st.last] - lnT[st.prev];
         st.sum_r = st.sum_r + r;
         st.sum_r2 = st.sum_r2 + r * r;
     }
+    st.ref2 = mid2p;
     st.steps_done += args.S;
     args.state[m] = st;
 }
@@ -899,7 +1041,14 @@ int validate(const cae_market *desc, uint32_t M)
         if ((uint64_t)d.n_noise + d.n_mom > d.A)
             return fail(CAE_EINVAL, "market %u: n_noise + n_mom > A", m);
         if (d.maker_half_spread >= d.L) return fail(CAE_EINVAL, "market %u: maker_half_spread >= L", m);
-        if (d.flags != 0) return fail(CAE_EINVAL, "market %u: flags must be 0", m);
+        const uint32_t model = d.flags & CAE_MODEL_MASK;
+        if (model != CAE_MODEL_LAST && model != CAE_MODEL_MID)
+            return fail(CAE_EINVAL, "market %u: unknown agent model %u", m, model);
+        if ((d.flags & 0xFF00u) != 0) return fail(CAE_EINVAL, "market %u: flags bits 8-15 must be 0", m);
+        if (model == CAE_MODEL_LAST && (d.flags >> CAE_PMKT_SHIFT) != 0)
+            return fail(CAE_EINVAL, "market %u: P_mkt needs the mid-price model", m);
+        if (model == CAE_MODEL_MID && d.K >= (1u << 20))
+            return fail(CAE_EINVAL, "market %u: K=%u too large for the mid-price model", m, d.K);
     }
     return CAE_OK;
 }
@@ -1086,6 +1235,7 @@ int build_schedule(cae_ensemble *e, const cae_tuning *tn, const uint32_t *ids,
         x.tpl = tpl_for(d.L);
         x.book_off = off;
         x.id = ids ? ids[m] : m;
+        x.flags = d.flags;
         off += 2ull * d.L;
         dm[m] = x;
     }
@@ -1197,6 +1347,7 @@ int cae_create(const cae_market *desc, uint32_t M, uint64_t seed, const uint32_t
         std::memset(&st[m], 0, sizeof(cae_state));
         st[m].last = desc[m].L / 2;
         st[m].prev = desc[m].L / 2;
+        st[m].ref2 = 2u * (desc[m].L / 2);
     }
     auto cleanup = [&](int code) {
         delete e;
@@ -1219,9 +1370,12 @@ int cae_create(const cae_market *desc, uint32_t M, uint64_t seed, const uint32_t
     return CAE_OK;
 }
 
-static int step_impl(cae_ensemble *e, uint32_t S, bool naive)
+static int step_impl(cae_ensemble *e, uint32_t S, bool naive, uint32_t *tr_price = nullptr,
+                     uint32_t *tr_vol = nullptr, uint64_t tr_ld = 0)
 {
     if (!e) return fail(CAE_EINVAL, "NULL ensemble");
+    if ((tr_price || tr_vol) && tr_ld < S) return fail(CAE_EINVAL, "trace row length %llu < S = %u",
+                                                        (unsigned long long)tr_ld, S);
     if (S == 0) return CAE_OK;
     for (uint32_t m = 0; m < e->M; ++m) {
         const unsigned __int128 tot = (unsigned __int128)(e->steps_done[m] + S) * e->desc[m].A * e->desc[m].Q;
@@ -1238,6 +1392,9 @@ static int step_impl(cae_ensemble *e, uint32_t S, bool naive)
     a.book = e->dev.book;
     a.state = e->dev.state;
     a.lnT = reinterpret_cast<const double *>(ws + e->lay.off_lnt);
+    a.tr_price = tr_price;
+    a.tr_vol = tr_vol;
+    a.tr_ld = tr_ld;
     a.n_items = e->n_items;
     a.n_claimers = e->grid;
     a.S = S;
@@ -1259,6 +1416,11 @@ static int step_impl(cae_ensemble *e, uint32_t S, bool naive)
 int cae_step(cae_ensemble *e, uint32_t S) { return step_impl(e, S, false); }
 
 int cae_step_naive(cae_ensemble *e, uint32_t S) { return step_impl(e, S, true); }
+
+int cae_step_traced(cae_ensemble *e, uint32_t S, uint32_t *dev_price, uint32_t *dev_volume, uint64_t ld)
+{
+    return step_impl(e, S, false, dev_price, dev_volume, ld);
+}
 
 int cae_last_step_ms(cae_ensemble *e, float *ms)
 {
@@ -1300,6 +1462,8 @@ int cae_write_state(cae_ensemble *e, const cae_state *host_state, uint32_t M, co
     for (uint32_t m = 0; m < M; ++m) {
         if (host_state[m].last >= e->desc[m].L || host_state[m].prev >= e->desc[m].L)
             return fail(CAE_EINVAL, "market %u: last/prev outside the grid", m);
+        if (host_state[m].ref2 > 2u * (e->desc[m].L - 1u) || host_state[m].reserved != 0)
+            return fail(CAE_EINVAL, "market %u: ref2 outside the grid or reserved != 0", m);
         const unsigned __int128 tot = (unsigned __int128)host_state[m].steps_done * e->desc[m].A * e->desc[m].Q;
         if (tot >= ((unsigned __int128)1 << 32)) return fail(CAE_EINVAL, "market %u: steps_done past the guard", m);
     }

@@ -32,8 +32,6 @@ __device__ __forceinline__ uint16_t f2bf(float f)  // round to nearest even
     return (uint16_t)(u >> 16);
 }
 
-__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
-
 __device__ __forceinline__ float silu(float z) { return z / (1.0f + expf(-z)); }
 
 __device__ __forceinline__ float dsilu(float z)

@@ -14,13 +14,13 @@ STATE_DTYPE = np.dtype([
     ("last", np.uint32), ("prev", np.uint32), ("steps_done", np.uint64),
     ("n_trade", np.uint64), ("sum_vol", np.uint64), ("sum_px", np.uint64),
     ("sum_spread", np.uint64), ("n_spread", np.uint64),
-    ("sum_r", np.float64), ("sum_r2", np.float64),
+    ("sum_r", np.float64), ("sum_r2", np.float64), ("ref2", np.uint32), ("reserved", np.uint32),
 ])
 MARKET_DTYPE = np.dtype([
     ("L", np.uint32), ("A", np.uint32), ("K", np.uint32), ("Q", np.uint32),
     ("n_noise", np.uint32), ("n_mom", np.uint32), ("h", np.uint32), ("flags", np.uint32),
 ])
-assert STATE_DTYPE.itemsize == C.sizeof(State) == 72
+assert STATE_DTYPE.itemsize == C.sizeof(State) == 80
 assert MARKET_DTYPE.itemsize == C.sizeof(Market) == 32
 
 
@@ -28,12 +28,23 @@ def _p(a):
     return a.ctypes.data_as(C.c_void_p)
 
 
-def markets(L, A, K, Q, M=1, n_noise=None, n_mom=0, h=2):
+def model_flags(model=_lib.MODEL_LAST, p_mkt=0.0):
+    """Descriptor flags for an agent model (MODEL_LAST / MODEL_MID) and, for the mid-price
+    model, the marketable-order probability P_mkt (rounded to a multiple of 2^-16)."""
+    p16 = int(round(float(p_mkt) * 65536))
+    if not 0 <= p16 < 65536:
+        raise ValueError("P_mkt must lie in [0, 1)")
+    if p16 and model != _lib.MODEL_MID:
+        raise ValueError("P_mkt needs the mid-price model")
+    return (p16 << _lib.PMKT_SHIFT) | int(model)
+
+
+def markets(L, A, K, Q, M=1, n_noise=None, n_mom=0, h=2, flags=0):
     """M identical market descriptors (structured numpy array)."""
     d = np.zeros(M, MARKET_DTYPE)
     d["L"], d["A"], d["K"], d["Q"] = L, A, K, Q
     d["n_noise"] = A if n_noise is None else n_noise
-    d["n_mom"], d["h"] = n_mom, h
+    d["n_mom"], d["h"], d["flags"] = n_mom, h, flags
     return d
 
 
@@ -127,6 +138,34 @@ class Ensemble:
         """Advance every market by S steps (one persistent launch, asynchronous)."""
         check("cae_step", lib().cae_step(self.handle, int(S)))
         self.steps += int(S)
+
+    def step_traced(self, S, price=True, volume=True, out=None, col=0):
+        """S steps that also record every market's per-step series (asynchronous).
+
+        Returns (price, volume): int32 device tensors of shape (M, S) holding the uint32 values
+        (the tick `last` after each step; the volume executed in it), or None for a series not
+        asked for.  out: optional (price, volume) tensors of shape (M, W) to fill at columns
+        [col, col + S) instead (either may be None)."""
+        import torch
+        S = int(S)
+        if out is None:
+            mk = lambda want: (torch.empty((self.M, S), dtype=torch.int32, device=self.device)
+                               if want else None)
+            pr, vo, ld, off = mk(price), mk(volume), S, 0
+        else:
+            pr, vo = out
+            ld = next(t.shape[1] for t in (pr, vo) if t is not None)
+            off = int(col)
+            for t in (pr, vo):
+                if t is not None and (t.dtype != torch.int32 or not t.is_contiguous()
+                                      or tuple(t.shape) != (self.M, ld) or t.device != self.device):
+                    raise ValueError("trace tensors must be contiguous int32 (M, W) on the device")
+            if off + S > ld:
+                raise ValueError("columns [%d, %d) exceed the trace width %d" % (off, off + S, ld))
+        ptr = lambda t: C.c_void_p(t.data_ptr() + 4 * off) if t is not None else None
+        check("cae_step_traced", lib().cae_step_traced(self.handle, S, ptr(pr), ptr(vo), ld))
+        self.steps += S
+        return pr, vo
 
     def step_naive(self, S):
         """The same S steps with the naive one-thread-per-market engine (ablation)."""

@@ -13,11 +13,11 @@ MARKET_DTYPE = np.dtype([
 ])
 
 
-def uniform(M, L, A, K, Q, n_noise=None, n_mom=0, h=2):
+def uniform(M, L, A, K, Q, n_noise=None, n_mom=0, h=2, flags=0):
     d = np.zeros(M, MARKET_DTYPE)
     d["L"], d["A"], d["K"], d["Q"] = L, A, K, Q
     d["n_noise"] = A if n_noise is None else n_noise
-    d["n_mom"], d["h"] = n_mom, h
+    d["n_mom"], d["h"], d["flags"] = n_mom, h, flags
     return d
 
 

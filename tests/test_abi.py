@@ -35,7 +35,7 @@ def test_exports_every_declared_symbol(cae):
 
 def test_struct_layouts(cae):
     assert C.sizeof(cae.Market) == 32
-    assert C.sizeof(cae.State) == 72
+    assert C.sizeof(cae.State) == 80
     assert C.sizeof(cae.Sizes) == 32
     assert C.sizeof(cae.Tuning) == 16 + 6 * cae.NUM_CLASSES
 
@@ -57,7 +57,7 @@ def test_sizes(cae):
     s = _sizes(d)
     assert s.book_words == 1024 * 2 * 256
     assert s.book_bytes == 4 * s.book_words
-    assert s.state_bytes == 72 * 1024
+    assert s.state_bytes == 80 * 1024
     assert s.workspace_bytes > 0 and s.workspace_bytes % 256 == 0
     mixed = np.concatenate([engine.markets(64, 10, 1, 1), engine.markets(1000, 10, 1, 1)])
     assert _sizes(mixed).book_words == 2 * 64 + 2 * 1000
@@ -65,7 +65,8 @@ def test_sizes(cae):
 
 @pytest.mark.parametrize("field,value", [("L", 0), ("L", 1025), ("A", 0), ("Q", 0),
                                          ("K", 2**30 + 1), ("n_noise", 11), ("h", 64),
-                                         ("flags", 1)])
+                                         ("flags", 2), ("flags", 0x100), ("flags", 5 << 16),
+                                         ("flags", 1 | (1 << 8))])
 def test_invalid_descriptors(cae, field, value):
     from paper_2606_21784_amd import engine
     d = engine.markets(64, 10, 4, 5, M=3)
@@ -74,6 +75,19 @@ def test_invalid_descriptors(cae, field, value):
         _sizes(d)
     assert ei.value.code == cae.CAE_EINVAL
     assert "market 1" in str(ei.value)
+
+
+def test_mid_model_descriptors(cae):
+    """The mid-price model takes P_mkt in the flags' upper half; its K must stay below 2^20."""
+    from paper_2606_21784_amd import engine
+    ok = engine.markets(64, 10, 4, 5, M=2, flags=engine.model_flags(cae.MODEL_MID, 0.25))
+    assert int(ok["flags"][0]) == (16384 << 16) | 1
+    _sizes(ok)
+    bad = engine.markets(64, 10, 2**20, 5, flags=engine.model_flags(cae.MODEL_MID))
+    with pytest.raises(cae.CaeError):
+        _sizes(bad)
+    with pytest.raises(ValueError):
+        engine.model_flags(cae.MODEL_LAST, 0.1)
 
 
 def test_agents_times_quantity_guard(cae):

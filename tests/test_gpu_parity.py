@@ -10,7 +10,7 @@ from paper_2606_21784_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 INT_FIELDS = ["last", "prev", "steps_done", "n_trade", "sum_vol", "sum_px", "sum_spread",
-              "n_spread"]
+              "n_spread", "ref2", "reserved"]
 
 
 def _engine():
@@ -348,5 +348,157 @@ def test_naive_engine_is_bit_identical(cfg):
     st, bk = ens.read_state(), ens.read_books()
     ens.close()
     rst, rbk = O.run(descs, 8, 40)
+    _assert_books(descs, bk, rbk)
+    _assert_states(st, rst)
+
+
+def _u32(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+@pytest.mark.parametrize("mode", ["lockstep", "single", "pipelined"])
+def test_traced_series_match_oracle(mode):
+    """cae_step_traced writes each market's per-step price and volume series equal to the
+    oracle's, in every schedule mode; untraced calls leave their columns alone and tracing does
+    not change books or states."""
+    import torch
+    E = _engine()
+    descs = W.uniform(9, 100, 300, 9, 20, n_noise=150, n_mom=90, h=3)
+    tn = {"lockstep": {"waves_per_group": 4, "waves_per_market": {c: 2 for c in range(40)}},
+          "single": {"waves_per_group": 4, "waves_per_market": {c: 1 for c in range(40)}},
+          "pipelined": {"waves_per_group": 4, "pipelined": {c: 1 for c in range(40)}}}[mode]
+    ens = E.Ensemble(descs, 21, tuning=tn)
+    pr = torch.full((9, 80), -1, dtype=torch.int32, device="cuda")
+    vo = torch.full((9, 80), -1, dtype=torch.int32, device="cuda")
+    ens.step_traced(30, out=(pr, vo), col=0)
+    ens.step(20)
+    ens.step_traced(30, out=(pr, vo), col=50)
+    p2, v2 = ens.step_traced(7)
+    _, v3 = ens.step_traced(5, price=False)
+    st, bk = ens.read_state(), ens.read_books()
+    ens.close()
+    rst, rbk, rpr, rvo = O.run(descs, 21, 92, trace=True)
+    _assert_books(descs, bk, rbk)
+    _assert_states(st, rst)
+    p, v = _u32(pr), _u32(vo)
+    assert rvo.max() < 2**32
+    for a, b in ((0, 30), (50, 80)):
+        np.testing.assert_array_equal(p[:, a:b], rpr[:, a:b])
+        np.testing.assert_array_equal(v[:, a:b], rvo[:, a:b].astype(np.uint32))
+    assert np.all(p[:, 30:50] == 0xFFFFFFFF) and np.all(v[:, 30:50] == 0xFFFFFFFF)
+    np.testing.assert_array_equal(_u32(p2), rpr[:, 80:87])
+    np.testing.assert_array_equal(_u32(v2), rvo[:, 80:87].astype(np.uint32))
+    np.testing.assert_array_equal(_u32(v3), rvo[:, 87:92].astype(np.uint32))
+
+
+def test_traced_mixed_sizes_and_modes():
+    """Traced series of markets of mixed L and A in one launch, with single-wave, lock-step and
+    pipelined classes side by side."""
+    import torch
+    E = _engine()
+    rng = np.random.default_rng(23)
+    n = 40
+    L = rng.choice([5, 64, 128, 256, 512, 1000], n)
+    A = rng.integers(1, 3000, n)
+    d = np.zeros(n, W.MARKET_DTYPE)
+    d["L"], d["A"], d["K"], d["Q"] = L, A, np.maximum(1, L // 16), rng.integers(1, 60, n)
+    d["n_noise"] = A // 2
+    d["n_mom"] = A // 3
+    d["h"] = np.minimum(2, L - 1)
+    cls = [E.size_class(int(a), int(b)) for a, b in zip(L, A)]
+    tn = {"waves_per_group": 8,
+          "waves_per_market": {c: (1 if c % 3 == 0 else 4) for c in set(cls)},
+          "pipelined": {c: 1 for c in set(cls) if c % 3 == 1}}
+    ens = E.Ensemble(d, 78, tuning=tn)
+    pr, vo = ens.step_traced(40)
+    torch.cuda.synchronize()
+    ens.close()
+    _, _, rpr, rvo = O.run(d, 78, 40, trace=True)
+    np.testing.assert_array_equal(_u32(pr), rpr)
+    np.testing.assert_array_equal(_u32(vo), rvo.astype(np.uint32))
+
+
+def test_traced_rejects_short_rows():
+    import ctypes as C
+    E = _engine()
+    from paper_2606_21784_amd import _lib
+    import torch
+    descs = W.uniform(3, 64, 64, 4, 5)
+    ens = E.Ensemble(descs, 1)
+    buf = torch.zeros((3, 8), dtype=torch.int32, device="cuda")
+    rc = _lib.lib().cae_step_traced(ens.handle, 10, C.c_void_p(buf.data_ptr()), None, 8)
+    assert rc == _lib.CAE_EINVAL
+    with pytest.raises(ValueError):
+        ens.step_traced(5, out=(buf, None), col=4)
+    st = ens.read_state()
+    ens.close()
+    assert np.all(st["steps_done"] == 0)
+
+
+def _mid(p_mkt):
+    return O.model_flags(O.MODEL_MID, int(round(p_mkt * 65536)))
+
+
+@pytest.mark.parametrize("mode", ["lockstep", "single", "pipelined"])
+@pytest.mark.parametrize("p_mkt", [0.0, 0.05, 0.6])
+def test_mid_model_matches_oracle(mode, p_mkt):
+    """The mid-price agent model (section III-C's rules, marketable orders with P_mkt): books,
+    states (with the momentum memory ref2) and traces equal the oracle's in every schedule mode,
+    across split calls."""
+    import torch
+    E = _engine()
+    descs = W.uniform(9, 100, 300, 9, 20, n_noise=150, n_mom=90, h=3, flags=_mid(p_mkt))
+    tn = {"lockstep": {"waves_per_group": 4, "waves_per_market": {c: 2 for c in range(40)}},
+          "single": {"waves_per_group": 4, "waves_per_market": {c: 1 for c in range(40)}},
+          "pipelined": {"waves_per_group": 4, "pipelined": {c: 1 for c in range(40)}}}[mode]
+    ens = E.Ensemble(descs, 31, tuning=tn)
+    ens.step(13)
+    pr, vo = ens.step_traced(40)
+    ens.step(7)
+    st, bk = ens.read_state(), ens.read_books()
+    ens.close()
+    rst, rbk = O.run(descs, 31, 13)
+    rst, rbk, rpr, rvo = O.run(descs, 31, 40, states=rst, book=rbk, trace=True)
+    rst, rbk = O.run(descs, 31, 7, states=rst, book=rbk)
+    _assert_books(descs, bk, rbk)
+    _assert_states(st, rst)
+    np.testing.assert_array_equal(_u32(pr), rpr)
+    np.testing.assert_array_equal(_u32(vo), rvo.astype(np.uint32))
+
+
+def test_models_mixed_in_one_launch():
+    """Last-tick and mid-price markets of mixed sizes in one launch, every schedule mode."""
+    E = _engine()
+    rng = np.random.default_rng(29)
+    n = 48
+    L = rng.choice([5, 64, 128, 256, 512, 1000], n)
+    A = rng.integers(1, 3000, n)
+    d = np.zeros(n, W.MARKET_DTYPE)
+    d["L"], d["A"], d["K"], d["Q"] = L, A, np.maximum(1, L // 16), rng.integers(1, 60, n)
+    d["n_noise"] = A // 2
+    d["n_mom"] = A // 3
+    d["h"] = np.minimum(2, L - 1)
+    d["flags"] = np.where(rng.random(n) < 0.5, 0, [_mid(x) for x in rng.choice([0.0, 0.1], n)])
+    cls = [E.size_class(int(a), int(b)) for a, b in zip(L, A)]
+    tn = {"waves_per_group": 8,
+          "waves_per_market": {c: (1 if c % 3 == 0 else 4) for c in set(cls)},
+          "pipelined": {c: 1 for c in set(cls) if c % 3 == 1}}
+    st, bk, _ = _run_gpu(d, 41, [11, 19], tuning=tn)
+    rst, rbk = O.run(d, 41, 30)
+    _assert_books(d, bk, rbk)
+    _assert_states(st, rst)
+
+
+@pytest.mark.parametrize("p_mkt", [0.0, 0.2])
+def test_naive_engine_mid_model(p_mkt):
+    E = _engine()
+    descs = W.uniform(70, 128, 256, 8, 10, n_noise=100, n_mom=100, h=2, flags=_mid(p_mkt))
+    ens = E.Ensemble(descs, 12)
+    ens.step_naive(15)
+    ens.step(10)
+    ens.step_naive(5)
+    st, bk = ens.read_state(), ens.read_books()
+    ens.close()
+    rst, rbk = O.run(descs, 12, 30)
     _assert_books(descs, bk, rbk)
     _assert_states(st, rst)
