@@ -258,6 +258,35 @@ def sweeps_leg():
     return out
 
 
+# Marketable-order probability of the mid-price model in the dynamics leg (the paper names
+# P_mkt without a value).
+DYN_P_MKT = 0.05
+
+
+def dynamics_leg():
+    """The agent-mix sweep of section IV-J (alpha_mom 0..0.70, makers 0.15, 64 markets of each
+    mix, 1000 steps, L = 128, K = 8, Q = 10) for A in {16, 64, 256, 1024}: one traced launch
+    of all 3840 markets per agent model, then the stylized facts from the recorded series."""
+    from paper_2606_21784_amd import dynamics, engine
+    from paper_2606_21784_amd._lib import MODEL_LAST, MODEL_MID
+    dynamics.run_sweep(A_values=(16,), alphas=(0.0,), markets=4, S=10)  # load / warm up
+    out = {"paper_rtx5090": "12.8e6-event sweep in under 0.25 s (section IV-J)"}
+    for name, flags in (("last_tick", engine.model_flags(MODEL_LAST)),
+                        ("mid_price_pmkt%.2f" % DYN_P_MKT, engine.model_flags(MODEL_MID, DYN_P_MKT))):
+        report, timing = dynamics.run_sweep(flags=flags)
+        out[name] = {
+            "timing": timing, "facts_A256": dynamics.facts(report, A=256),
+            "sweep": {str(A): {k: report[A][k] for k in ("alpha_mom", "tick_change_std",
+                                                         "price_std", "excess_kurtosis",
+                                                         "mean_volume", "mean_spread")}
+                      for A in report},
+            "acf_A256_alpha015": {k: report[256][k][3] for k in ("acf_r", "acf_abs_r")}}
+        log("dynamics %s: %d markets x %d steps, %.3g events in %.2f ms (%.3g events/s)" %
+            (name, timing["markets"], timing["steps"], timing["events"], timing["kernel_ms"],
+             timing["events_per_s"]))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -273,6 +302,8 @@ def main():
                     help="skip the sweep leg (paper shapes, step latency, market-count sweep)")
     ap.add_argument("--no-ablation", action="store_true",
                     help="skip the naive-engine ablation leg")
+    ap.add_argument("--no-dynamics", action="store_true",
+                    help="skip the agent-mix dynamics leg (traced sweep, stylized facts)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="after timing, copy 1 GiB device-to-device (counter calibration)")
     args = ap.parse_args()
@@ -371,6 +402,8 @@ def main():
         result["ablation"] = ablation_leg()
     if not args.no_sweeps:
         result["sweeps"] = sweeps_leg()
+    if not args.no_dynamics:
+        result["dynamics"] = dynamics_leg()
     if not args.no_uneven:
         result["uneven"] = uneven_leg()
     if not args.no_surrogate:
