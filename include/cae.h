@@ -244,7 +244,8 @@ int cae_clear(uint32_t L, uint32_t M, uint32_t *dev_book, uint32_t *dev_pstar,
  *
  * Parameter layout (fp32, row-major, input index first), P = cae_mlp_sizes().n_params floats:
  *   W1[d_in][H], b1[H], W2[H][H], b2[H], W3[H][d_out], b3[d_out]
- * bfloat16 weight copies (n_weights halfwords): W1, W2, W3 in the same layouts, back to back.
+ * bfloat16 weight copies (n_weights halfwords): W1, W2, W3 in the same layouts, back to back,
+ * then W2 transposed (W2T[n][k] = W2[k][n], H * H halfwords) for cae_mlp_predict.
  * bfloat16 (round to nearest even) is stored for the inputs, weights, hidden activations and
  * back-propagated gradients; products are accumulated in fp32; biases, pre-activations,
  * outputs, weight gradients and Adam moments are fp32.
@@ -272,6 +273,13 @@ int cae_mlp_refresh_weights(const cae_mlp *net, void *stream);
 /* y[N][d_out] (fp32, device) = network(x[N][d_in] (fp32, device)).  ws (device, workspace_bytes
  * for a batch >= N) receives the activations that cae_mlp_backward reuses.  Asynchronous. */
 int cae_mlp_forward(const cae_mlp *net, const float *x, float *y, uint32_t N, void *ws, void *stream);
+
+/* Inference only: y[N][d_out] = network(x[N][d_in]) in one fused launch (all three layers per
+ * tile of 32 samples, activations kept on chip), with no workspace and no limit on N.  The
+ * outputs are bit-identical to cae_mlp_forward's (same matrix-core tiles, summation order and
+ * bfloat16 rounding points); nothing is kept for cae_mlp_backward.  Requires d_hidden <= 496.
+ * Asynchronous.  Errors: CAE_EINVAL (shape, NULL), CAE_EHIP. */
+int cae_mlp_predict(const cae_mlp *net, const float *x, float *y, uint32_t N, void *stream);
 
 /* Gradient of sum_{n,k} dy[n][k] * y[n][k] with respect to every parameter, summed over the N
  * samples, written to grads (device, n_params fp32 in the parameter layout).  ws must hold the

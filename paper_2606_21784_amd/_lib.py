@@ -67,7 +67,8 @@ class CaeError(RuntimeError):
 EXPORTS = ["cae_strerror", "cae_last_error", "cae_device_info", "cae_sizes", "cae_create",
            "cae_step", "cae_step_naive", "cae_step_traced", "cae_read_books", "cae_read_state", "cae_write_state", "cae_get_tuning",
            "cae_last_step_ms", "cae_destroy", "cae_clear", "cae_mlp_sizes",
-           "cae_mlp_refresh_weights", "cae_mlp_forward", "cae_mlp_backward", "cae_mlp_adam",
+           "cae_mlp_refresh_weights", "cae_mlp_forward", "cae_mlp_predict", "cae_mlp_backward",
+           "cae_mlp_adam",
            "cae_mlp_loss_grad"]
 
 _lib = None
@@ -102,6 +103,7 @@ def lib():
     L.cae_mlp_sizes.argtypes = [u32, u32, u32, u32, P]
     L.cae_mlp_refresh_weights.argtypes = [P, P]
     L.cae_mlp_forward.argtypes = [P, P, P, u32, P, P]
+    L.cae_mlp_predict.argtypes = [P, P, P, u32, P]
     L.cae_mlp_backward.argtypes = [P, P, P, P, u32, P, P]
     L.cae_mlp_adam.argtypes = [P, P, P, P, u32, f32, f32, f32, f32, P]
     L.cae_mlp_loss_grad.argtypes = [P, P, P, P, u32, i32, f32, P]

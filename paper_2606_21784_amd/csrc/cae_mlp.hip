@@ -10,7 +10,9 @@
 // v_mfma_f32_16x16x16bf16_1k; biases, pre-activations, outputs, weight gradients and the Adam
 // state are fp32.  Parameter layout (row-major, input index first):
 //   W1[d_in][H], b1[H], W2[H][H], b2[H], W3[H][d_out], b3[d_out]
-// and the bfloat16 weight copies are W1, W2, W3 in the same layouts, back to back.
+// and the bfloat16 weight copies are W1, W2, W3 in the same layouts, back to back, followed by
+// W2 transposed (W2T[n][k] = W2[k][n]) for the fused inference kernel, whose matrix-core
+// operands want four consecutive input indices per lane.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -167,6 +169,7 @@ __global__ void __launch_bounds__(1024) loss_grad(const float *y, const float *t
 
 struct Layout {
     uint64_t w1, b1, w2, b2, w3, b3, P;  // param offsets
+    uint64_t w2t;                        // bf16 offset of the transposed W2 copy
     uint64_t W;                          // bf16 weight count
 };
 
@@ -180,7 +183,8 @@ __host__ __device__ inline Layout layout(uint32_t din, uint32_t H, uint32_t dout
     l.w3 = l.b2 + H;
     l.b3 = l.w3 + (uint64_t)H * dout;
     l.P = l.b3 + dout;
-    l.W = (uint64_t)din * H + (uint64_t)H * H + (uint64_t)H * dout;
+    l.w2t = (uint64_t)din * H + (uint64_t)H * H + (uint64_t)H * dout;
+    l.W = l.w2t + (uint64_t)H * H;
     return l;
 }
 
@@ -205,6 +209,140 @@ __global__ void adam_step(float *p, const float *g, float *m, float *v, uint16_t
         else if (i >= l.w2 && i < l.b2) w = (int64_t)(l.b1 + (i - l.w2));
         else if (i >= l.w3 && i < l.b3) w = (int64_t)(l.b1 + (l.b2 - l.w2) + (i - l.w3));
         if (w >= 0) wb[w] = f2bf(pi);
+        if (i >= l.w2 && i < l.b2) {  // W2[k][n] -> W2T[n][k]
+            const uint64_t H = l.w3 - l.b2;
+            const uint64_t k = (i - l.w2) / H, n = (i - l.w2) % H;
+            wb[l.w2t + n * H + k] = f2bf(pi);
+        }
+    }
+}
+
+// Inference of the whole network for kPredRows rows per workgroup (four waves), in one launch.
+// The input tile and both hidden activations stay in LDS (bf16, rows padded by 8 elements);
+// the layer products use the same MFMA tiles, k order and rounding points as mlp_gemm, so the
+// outputs equal cae_mlp_forward's bit for bit.
+constexpr uint32_t kPredRows = 32;
+constexpr uint32_t kPredPad = 8;
+constexpr uint32_t kPredMaxH = 496;  // keeps the workgroup's LDS within 64 KiB
+
+struct PredArgs {
+    const float *x;
+    float *y;
+    uint32_t N, din, H, dout;
+    const uint16_t *W1, *W2T, *W3;
+    const float *b1, *b2, *b3;
+};
+
+__device__ __forceinline__ v4s lds_frag(const uint16_t *p)  // four consecutive bf16
+{
+    const uint2 v = *reinterpret_cast<const uint2 *>(p);
+    v4s r;
+    r[0] = (short)(v.x & 0xFFFFu);
+    r[1] = (short)(v.x >> 16);
+    r[2] = (short)(v.y & 0xFFFFu);
+    r[3] = (short)(v.y >> 16);
+    return r;
+}
+
+__global__ void __launch_bounds__(256) mlp_predict(const PredArgs a)
+{
+    extern __shared__ __align__(16) uint16_t plds[];
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+    const uint32_t r16 = lane & 15u, grp = lane >> 4;
+    const uint32_t row0 = blockIdx.x * kPredRows;
+    const uint32_t Kx = (a.din + 15u) & ~15u;  // input width padded to the MFMA depth
+    const uint32_t ldh = a.H + kPredPad;
+    uint16_t *xs = plds;                        // [kPredRows][Kx]
+    uint16_t *h1 = xs + kPredRows * Kx;          // [kPredRows][ldh]
+    uint16_t *h2 = h1 + kPredRows * ldh;         // [kPredRows][ldh]
+    for (uint32_t i = threadIdx.x; i < kPredRows * Kx; i += 256u) {
+        const uint32_t r = i / Kx, c = i % Kx;
+        xs[i] = (row0 + r < a.N && c < a.din) ? f2bf(a.x[(size_t)(row0 + r) * a.din + c]) : (uint16_t)0;
+    }
+    __syncthreads();
+    const uint32_t ct = a.H / 16u;  // column tiles of a hidden layer
+    // layer 1: h1 = silu(x W1 + b1)
+    for (uint32_t j = wave; j < ct; j += 4u) {
+        const uint32_t n = 16u * j + r16;
+#pragma unroll
+        for (uint32_t rt = 0; rt < kPredRows / 16u; ++rt) {
+            v4f acc = {0.f, 0.f, 0.f, 0.f};
+            for (uint32_t k0 = 0; k0 < Kx; k0 += 16u) {
+                const v4s av = lds_frag(xs + (16u * rt + r16) * Kx + k0 + 4u * grp);
+                v4s bv;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const uint32_t k = k0 + 4u * grp + (uint32_t)t;
+                    bv[t] = (short)(k < a.din ? a.W1[(size_t)k * a.H + n] : (uint16_t)0);
+                }
+                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const float z = acc[t] + a.b1[n];
+                h1[(16u * rt + 4u * grp + (uint32_t)t) * ldh + n] = f2bf(silu(z));
+            }
+        }
+    }
+    __syncthreads();
+    // layer 2: h2 = silu(h1 W2 + b2), B fragments from W2T (8 bytes per lane)
+    for (uint32_t j = wave; j < ct; j += 4u) {
+        const uint32_t n = 16u * j + r16;
+        v4f acc[kPredRows / 16u];
+#pragma unroll
+        for (uint32_t rt = 0; rt < kPredRows / 16u; ++rt) acc[rt] = v4f{0.f, 0.f, 0.f, 0.f};
+        const uint16_t *wrow = a.W2T + (size_t)n * a.H + 4u * grp;
+        for (uint32_t k0 = 0; k0 < a.H; k0 += 128u) {
+            v4s bv[8];
+#pragma unroll
+            for (uint32_t u = 0; u < 8u; ++u)
+                if (k0 + 16u * u < a.H) {
+                    const uint2 v = *reinterpret_cast<const uint2 *>(wrow + k0 + 16u * u);
+                    bv[u][0] = (short)(v.x & 0xFFFFu);
+                    bv[u][1] = (short)(v.x >> 16);
+                    bv[u][2] = (short)(v.y & 0xFFFFu);
+                    bv[u][3] = (short)(v.y >> 16);
+                }
+#pragma unroll
+            for (uint32_t u = 0; u < 8u; ++u)
+                if (k0 + 16u * u < a.H) {
+#pragma unroll
+                    for (uint32_t rt = 0; rt < kPredRows / 16u; ++rt) {
+                        const v4s av = lds_frag(h1 + (16u * rt + r16) * ldh + k0 + 16u * u + 4u * grp);
+                        acc[rt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv[u], acc[rt], 0, 0, 0);
+                    }
+                }
+        }
+#pragma unroll
+        for (uint32_t rt = 0; rt < kPredRows / 16u; ++rt)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const float z = acc[rt][t] + a.b2[n];
+                h2[(16u * rt + 4u * grp + (uint32_t)t) * ldh + n] = f2bf(silu(z));
+            }
+    }
+    __syncthreads();
+    // layer 3: y = h2 W3 + b3 (one column tile, one row tile per wave)
+    if (wave < kPredRows / 16u) {
+        const uint32_t rt = wave, n = r16;
+        v4f acc = {0.f, 0.f, 0.f, 0.f};
+        for (uint32_t k0 = 0; k0 < a.H; k0 += 16u) {
+            const v4s av = lds_frag(h2 + (16u * rt + r16) * ldh + k0 + 4u * grp);
+            v4s bv;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const uint32_t k = k0 + 4u * grp + (uint32_t)t;
+                bv[t] = (short)(n < a.dout ? a.W3[(size_t)k * a.dout + n] : (uint16_t)0);
+            }
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
+        }
+        if (n < a.dout) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const uint32_t r = row0 + 16u * rt + 4u * grp + (uint32_t)t;
+                if (r < a.N) a.y[(size_t)r * a.dout + n] = acc[t] + a.b3[n];
+            }
+        }
     }
 }
 
@@ -375,6 +513,34 @@ int cae_mlp_forward(const cae_mlp *net, const float *x, float *y, uint32_t N, vo
     g.Of = y;
     g.ldo = dout;
     gemm<false, false, EPI_OUTPUT>(g, s);
+    return launch_status();
+}
+
+int cae_mlp_predict(const cae_mlp *net, const float *x, float *y, uint32_t N, void *stream)
+{
+    int rc = check_net(net);
+    if (rc) return rc;
+    if (!x || !y) return mfail(CAE_EINVAL, "NULL x or y");
+    if (net->d_hidden > kPredMaxH) return mfail(CAE_EINVAL, "cae_mlp_predict needs d_hidden <= 496");
+    if (N == 0) return CAE_OK;
+    const uint32_t din = net->d_in, H = net->d_hidden, dout = net->d_out;
+    const Layout l = layout(din, H, dout);
+    PredArgs a;
+    a.x = x;
+    a.y = y;
+    a.N = N;
+    a.din = din;
+    a.H = H;
+    a.dout = dout;
+    a.W1 = net->weights;
+    a.W2T = net->weights + l.w2t;
+    a.W3 = net->weights + (size_t)din * H + (size_t)H * H;
+    a.b1 = net->params + l.b1;
+    a.b2 = net->params + l.b2;
+    a.b3 = net->params + l.b3;
+    const size_t lds = 2ull * (kPredRows * ((din + 15u) & ~15u) + 2ull * kPredRows * (H + kPredPad));
+    const uint32_t blocks = (N + kPredRows - 1u) / kPredRows;
+    hipLaunchKernelGGL(mlp_predict, dim3(blocks), dim3(256), lds, (hipStream_t)stream, a);
     return launch_status();
 }
 

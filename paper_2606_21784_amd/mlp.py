@@ -75,6 +75,18 @@ class MLP:
         self._last_n = n
         return y
 
+    def predict(self, x, y=None):
+        """Inference only (one fused launch, any batch size): the same outputs as ``forward``,
+        keeping nothing for ``backward``."""
+        import torch
+        n = int(x.shape[0])
+        assert x.dtype == torch.float32 and x.is_contiguous() and x.shape[1] == self.dims[0]
+        if y is None:
+            y = torch.empty((n, self.dims[2]), dtype=torch.float32, device=self.device)
+        check("cae_mlp_predict", lib().cae_mlp_predict(C.byref(self.net), x.data_ptr(), y.data_ptr(), n,
+                                                       self.stream))
+        return y
+
     def backward(self, x, dy):
         """Gradients (fp32, parameter layout) of sum(dy * y) for the last forward's batch."""
         n = int(dy.shape[0])

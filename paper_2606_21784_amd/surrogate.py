@@ -129,11 +129,7 @@ def train(net, X, Z, epochs=300, batch=1024, lr=3e-3, lr_min=1e-5, seed=0, huber
 def predict(net, X, scaler, batch=None):
     import torch
     xd = torch.from_numpy(np.ascontiguousarray(X)).to(net.device)
-    out = []
-    bs = batch or net.max_batch
-    for i in range(0, len(X), bs):
-        out.append(net.forward(xd[i:i + bs].contiguous()).cpu().numpy())
-    return scaler.inv(np.concatenate(out))
+    return scaler.inv(net.predict(xd).cpu().numpy())
 
 
 def rel_err(pred, exact):
@@ -208,8 +204,7 @@ def fit_and_evaluate(data, epochs=300, hidden=256, batch=1024, lr=3e-3, huber_de
     times = []
     for _ in range(7):
         e0.record()
-        for i in range(0, len(Xte), net.max_batch):
-            net.forward(xd[i:i + net.max_batch])
+        net.predict(xd)
         e1.record()
         torch.cuda.synchronize()
         times.append(e0.elapsed_time(e1) * 1e-3)
@@ -256,10 +251,7 @@ def calibration_demo(net, scaler, data, n_targets=16, n_candidates=65536, verify
         Yt = data["Yte"][ti]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        pred = []
-        for i in range(0, n_candidates, net.max_batch):
-            pred.append(net.forward(Xc[i:i + net.max_batch]).cpu().numpy())
-        P = scaler.inv(np.concatenate(pred))
+        P = scaler.inv(net.predict(Xc).cpu().numpy())
         best = np.argsort(_log_dist(P, Yt[None, :]))[:verify]
         Yv = exact_stats(cand[best], base + best, data["seed"], data["S"], data["markets_per_draw"])
         dv = _log_dist(Yv, Yt[None, :])

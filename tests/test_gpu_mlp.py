@@ -38,6 +38,42 @@ def test_forward_matches_oracle(dims, N):
     assert _rel(y, yo) < 2e-3, _rel(y, yo)
 
 
+@pytest.mark.parametrize("dims,N", [((4, 256, 3), 6553), ((7, 48, 5), 33), ((1, 16, 1), 1),
+                                    ((4, 256, 3), 32), ((33, 496, 16), 65), ((4, 256, 3), 100000)])
+def test_predict_equals_forward(dims, N):
+    """The fused inference kernel gives cae_mlp_forward's outputs bit for bit (same tiles, order
+    and rounding points), for ragged batches and any N, and so the oracle's within tolerance."""
+    import torch
+    M = _mlp()
+    chunk = min(N, 8192)
+    net = M.MLP(*dims, max_batch=chunk, seed=4)
+    rng = np.random.default_rng(5)
+    p = net.get_params().astype(np.float64)
+    p[dims[0] * dims[1]:dims[0] * dims[1] + dims[1]] = rng.normal(0, 0.1, dims[1])
+    net.set_params(p)
+    x = torch.from_numpy(rng.normal(0, 1, (N, dims[0])).astype(np.float32)).cuda()
+    yp = net.predict(x).cpu().numpy()
+    yf = np.concatenate([net.forward(x[i:i + chunk].contiguous()).cpu().numpy()
+                         for i in range(0, N, chunk)])
+    np.testing.assert_array_equal(yp, yf)
+    k = min(N, 300)
+    yo = OM.forward(net.get_params().astype(np.float64), dims, x[:k].cpu().numpy().astype(np.float64),
+                    round_bf16=True)
+    assert _rel(yp[:k], yo) < 2e-3, _rel(yp[:k], yo)
+
+
+def test_predict_rejects_wide_hidden_layer():
+    import ctypes as C
+    M = _mlp()
+    from paper_2606_21784_amd import _lib
+    import torch
+    net = M.MLP(4, 512, 3, max_batch=16, seed=0)
+    x = torch.zeros((4, 4), dtype=torch.float32, device="cuda")
+    y = torch.zeros((4, 3), dtype=torch.float32, device="cuda")
+    rc = _lib.lib().cae_mlp_predict(C.byref(net.net), x.data_ptr(), y.data_ptr(), 4, None)
+    assert rc == _lib.CAE_EINVAL
+
+
 @pytest.mark.parametrize("dims,N", [((4, 256, 3), 256), ((7, 48, 5), 37)])
 def test_backward_matches_oracle(dims, N):
     import torch
@@ -79,7 +115,7 @@ def test_adam_matches_oracle():
     W = net.weights.cpu().numpy().view(np.uint16).astype(np.uint32) << 16
     Wf = W.view(np.float32)
     W1, b1, W2, b2, W3, b3 = OM.split(net.get_params(), dims)
-    ref = np.concatenate([W1.ravel(), W2.ravel(), W3.ravel()])
+    ref = np.concatenate([W1.ravel(), W2.ravel(), W3.ravel(), W2.T.ravel()])
     np.testing.assert_array_equal(Wf, OM.bf16(ref).astype(np.float32))
 
 
