@@ -383,10 +383,12 @@ struct OrderCtx {
     bool mid;
 };
 
+// MID: the code may meet mid-price markets (false compiles the last-tick rules alone).
+template <bool MID>
 __device__ __forceinline__ OrderCtx order_ctx(const DevMarket &d, uint32_t s, const Refs &r)
 {
     OrderCtx o;
-    o.mid = (d.flags & CAE_MODEL_MASK) == CAE_MODEL_MID;
+    o.mid = MID && (d.flags & CAE_MODEL_MASK) == CAE_MODEL_MID;
     o.span = 2u * d.K + 1u;
     o.twoK = 2u * d.K;
     o.Q = d.Q;
@@ -441,31 +443,31 @@ __device__ __forceinline__ uint32_t mid_noise_word(const OrderCtx &o, uint32_t w
 }
 
 // MOMENTUM (a < mom_end) or MAKER agent a, either model.
+template <bool MID>
 __device__ __forceinline__ uint32_t other_word(const OrderCtx &o, uint32_t a, uint32_t w0, uint32_t w3)
 {
-    uint32_t sell;
-    int tick;
-    if (a < o.mom_end) {
-        sell = o.mom_dir == 2u ? (w0 >> 31) : o.mom_dir;
-        tick = sell ? o.mom_ask : o.mom_bid;
-        if (w3 < o.tmkt) tick = sell ? 0 : o.top;
-    } else {  // MAKER: buy when a + s is even
-        sell = (a ^ o.s) & 1u;
-        tick = sell ? o.mk_ask : o.mk_bid;
-    }
+    // tick = bid tick + sell x (ask tick - bid tick), written as arithmetic so that the four
+    // candidate ticks are not gathered into an indexed table in private memory
+    const bool mom = a < o.mom_end;
+    const uint32_t sell = mom ? (o.mom_dir == 2u ? (w0 >> 31) : o.mom_dir) : ((a ^ o.s) & 1u);
+    const int lo = mom ? o.mom_bid : o.mk_bid;
+    const int span = mom ? o.mom_ask - o.mom_bid : o.mk_ask - o.mk_bid;
+    int tick = lo + (int)sell * span;
+    if (MID && mom && w3 < o.tmkt) tick = sell ? 0 : o.top;
     tick = min(max(tick, 0), o.top);
     return 2u * (uint32_t)tick + sell;
 }
 
 // Every order of one market-step, added into the LDS book (interleaved pairs: word 2*tick+side).
+template <bool MID>
 __device__ __forceinline__ void gen_orders(const DevMarket &d, uint32_t m, uint32_t s, const Refs &r,
                                            uint32_t key0, uint32_t key1, uint32_t t, uint32_t nthr,
                                            uint32_t *bk)
 {
     const PhiloxStep ph(s, m, key0, key1);
-    const OrderCtx o = order_ctx(d, s, r);
+    const OrderCtx o = order_ctx<MID>(d, s, r);
     uint32_t a = t;
-    if (o.mid) {
+    if (MID && o.mid) {
         for (; a < d.n_noise; a += nthr) {
             uint32_t w0, w1, w2, w3;
             ph.words4(a, w0, w1, w2, w3);
@@ -479,9 +481,10 @@ __device__ __forceinline__ void gen_orders(const DevMarket &d, uint32_t m, uint3
         }
     }
     for (; a < d.A; a += nthr) {
-        uint32_t w0, w1, w2, w3;
-        ph.words4(a, w0, w1, w2, w3);
-        atomicAdd(&bk[other_word(o, a, w0, w3)], order_qty(o, w2));
+        uint32_t w0, w1, w2, w3 = 0;
+        if constexpr (MID) ph.words4(a, w0, w1, w2, w3);
+        else ph.words(a, w0, w1, w2);
+        atomicAdd(&bk[other_word<MID>(o, a, w0, w3)], order_qty(o, w2));
     }
 }
 
@@ -511,7 +514,7 @@ __device__ __forceinline__ uint32_t next_mid2(bool mid, uint32_t bb, uint32_t ba
 
 // One market (or an idle slot of a lock-step item) for all S steps.  MULTI: the market spans
 // several waves and the workgroup barrier separates the phases (Algorithm 1's barriers).
-template <int TPL_MAX, bool MULTI>
+template <int TPL_MAX, bool MULTI, bool MID, bool TRACE>
 __device__ __forceinline__ void run_market(const EngineArgs &args, const Item &item, uint32_t sub,
                                            uint32_t w_in, uint32_t lane, bool active,
                                            uint32_t *lds)
@@ -555,9 +558,9 @@ __device__ __forceinline__ void run_market(const EngineArgs &args, const Item &i
     }
     if constexpr (MULTI) __syncthreads();
     else wave_sync();
-    const bool mid = (d.flags & CAE_MODEL_MASK) == CAE_MODEL_MID;
+    const bool mid = MID && (d.flags & CAE_MODEL_MASK) == CAE_MODEL_MID;
     mid2 = 2u * last;
-    if (active && mid) {
+    if (MID && active && mid) {
         uint32_t bb, ba;
         book_ends(bk, d.tpl, lane, bb, ba);
         mid2 = next_mid2(true, bb, ba, last);
@@ -566,7 +569,7 @@ __device__ __forceinline__ void run_market(const EngineArgs &args, const Item &i
     const double *lnT = args.lnT + d.L;  // ln(L + tick)
     for (uint32_t i = 0; i < args.S; ++i) {
         const uint32_t s = (uint32_t)steps0 + i;
-        if (active) gen_orders(d, d.id, s, Refs{last, prev, mid2, mid2p}, args.k0, args.k1, t, nthr, bk);
+        if (active) gen_orders<MID>(d, d.id, s, Refs{last, prev, mid2, mid2p}, args.k0, args.k1, t, nthr, bk);
         if constexpr (MULTI) __syncthreads();
         else wave_sync();
         ClearOut co;
@@ -602,7 +605,9 @@ __device__ __forceinline__ void run_market(const EngineArgs &args, const Item &i
             const double r = lnT[last] - lnT[prev];
             sum_r = sum_r + r;
             sum_r2 = sum_r2 + r * r;
-            if (t == 0) trace_step(args, m, i, last, co.v);
+            if constexpr (TRACE) {
+                if (t == 0) trace_step(args, m, i, last, co.v);
+            }
         }
     }
     if (active) {
@@ -652,7 +657,7 @@ __device__ __forceinline__ void st_u64(uint32_t *p, uint64_t v)
 // G-1 waves generate and aggregate the other market's orders.  One barrier per phase; no wave
 // waits for a clearing.  With one market the phases alternate between its orders and its
 // clearing.  Phase count: 2S (+1 to clear B's last step).
-template <int TPL_MAX>
+template <int TPL_MAX, bool MID, bool TRACE>
 __device__ __forceinline__ void run_pair(const EngineArgs &args, const Item &item, uint32_t wave, uint32_t lane,
                                          uint32_t G, uint32_t *lds)
 {
@@ -698,7 +703,7 @@ __device__ __forceinline__ void run_pair(const EngineArgs &args, const Item &ite
             uint32_t *scr = bk + item.stride - kScr;
             const uint32_t last = (uint32_t)__builtin_amdgcn_readfirstlane((int)scr[0]);
             uint32_t mid2 = 2u * last;
-            if ((dm.flags & CAE_MODEL_MASK) == CAE_MODEL_MID) {
+            if (MID && (dm.flags & CAE_MODEL_MASK) == CAE_MODEL_MID) {
                 uint32_t bb, ba;
                 book_ends(bk, dm.tpl, lane, bb, ba);
                 mid2 = next_mid2(true, bb, ba, last);
@@ -746,10 +751,12 @@ __device__ __forceinline__ void run_pair(const EngineArgs &args, const Item &ite
                 }
                 const double *lnT = args.lnT + dy.L;
                 const double r = lnT[last] - lnT[last0];
-                if (lane == 0) trace_step(args, Y ? mB : mA, (p - 1u) >> 1, last, co.v);
+                if constexpr (TRACE) {
+                    if (lane == 0) trace_step(args, Y ? mB : mA, (p - 1u) >> 1, last, co.v);
+                }
                 const uint32_t mid2_used = (uint32_t)__builtin_amdgcn_readfirstlane((int)scr[20]);
                 const uint32_t mid2_next =
-                    next_mid2((dy.flags & CAE_MODEL_MASK) == CAE_MODEL_MID, co.bb, co.ba, last);
+                    next_mid2(MID && (dy.flags & CAE_MODEL_MASK) == CAE_MODEL_MID, co.bb, co.ba, last);
                 if (lane == 0) {
                     scr[18] = mid2_used;
                     scr[20] = mid2_next;
@@ -772,12 +779,12 @@ __device__ __forceinline__ void run_pair(const EngineArgs &args, const Item &ite
             const uint32_t s = (uint32_t)__builtin_amdgcn_readfirstlane((int)s0.z) + (p >> 1);
             const DevMarket &dx = X ? dB : dA;
             Refs r{last, prev, 0u, 0u};
-            if ((dx.flags & CAE_MODEL_MASK) == CAE_MODEL_MID) {
+            if (MID && (dx.flags & CAE_MODEL_MASK) == CAE_MODEL_MID) {
                 const uint32_t *scr = bk + item.stride - kScr;
                 r.mid2p = (uint32_t)__builtin_amdgcn_readfirstlane((int)scr[18]);
                 r.mid2 = (uint32_t)__builtin_amdgcn_readfirstlane((int)scr[20]);
             }
-            gen_orders(dx, dx.id, s, r, args.k0, args.k1, (gidx << 6) | lane, (G - 1u) << 6, bk);
+            gen_orders<MID>(dx, dx.id, s, r, args.k0, args.k1, (gidx << 6) | lane, (G - 1u) << 6, bk);
         }
         __syncthreads();
         gidx = gidx == 0u ? G - 1u : gidx - 1u;
@@ -802,7 +809,9 @@ __device__ __forceinline__ void run_pair(const EngineArgs &args, const Item &ite
     }
 }
 
-template <int TPL_MAX>
+// MID: some market may use the mid-price model; TRACE: record the per-step series.  Each
+// instantiation carries only the code it needs, which keeps scalar registers for the step loop.
+template <int TPL_MAX, bool MID, bool TRACE>
 __global__ void __launch_bounds__(1024) cae_engine_kernel(const EngineArgs args)
 {
     extern __shared__ __align__(16) uint32_t lds[];
@@ -823,11 +832,11 @@ __global__ void __launch_bounds__(1024) cae_engine_kernel(const EngineArgs args)
         const uint32_t w_in = wave & ((1u << item.wpm_log2) - 1u);
         const bool active = sub < item.count;
         if (item.pipe) {
-            run_pair<TPL_MAX>(args, item, wave, lane, blockDim.x >> 6, lds);
+            run_pair<TPL_MAX, MID, TRACE>(args, item, wave, lane, blockDim.x >> 6, lds);
         } else if (item.wpm_log2 == 0) {
-            if (active) run_market<TPL_MAX, false>(args, item, sub, w_in, lane, true, lds);
+            if (active) run_market<TPL_MAX, false, MID, TRACE>(args, item, sub, w_in, lane, true, lds);
         } else {
-            run_market<TPL_MAX, true>(args, item, sub, w_in, lane, active, lds);
+            run_market<TPL_MAX, true, MID, TRACE>(args, item, sub, w_in, lane, active, lds);
         }
         __syncthreads();
     }
@@ -867,11 +876,11 @@ __global__ void __launch_bounds__(64) cae_naive_kernel(const EngineArgs args, ui
     for (uint32_t i = 0; i < args.S; ++i) {
         const uint32_t s = (uint32_t)st.steps_done + i;
         const PhiloxStep ph(s, d.id, args.k0, args.k1);
-        const OrderCtx o = order_ctx(d, s, Refs{st.last, st.prev, mid2, mid2p});
+        const OrderCtx o = order_ctx<true>(d, s, Refs{st.last, st.prev, mid2, mid2p});
         for (uint32_t a = 0; a < d.A; ++a) {
             uint32_t w0, w1, w2, w3;
             ph.words4(a, w0, w1, w2, w3);
-            const uint32_t w = a >= d.n_noise ? other_word(o, a, w0, w3)
+            const uint32_t w = a >= d.n_noise ? other_word<true>(o, a, w0, w3)
                                : mid          ? mid_noise_word(o, w0, w1, w3)
                                               : noise_word(o, w0, w1);
             const uint32_t q = order_qty(o, w2);
@@ -1085,15 +1094,24 @@ int device_cus(int dev, uint32_t *num_cu)
 
 using EngineFn = void (*)(const EngineArgs);
 
-EngineFn engine_fn(uint32_t tpl_max)
+template <bool MID, bool TRACE>
+EngineFn engine_fn_t(uint32_t tpl_max)
 {
     switch (tpl_max) {
-    case 1: return cae_engine_kernel<1>;
-    case 2: return cae_engine_kernel<2>;
-    case 4: return cae_engine_kernel<4>;
-    case 8: return cae_engine_kernel<8>;
-    default: return cae_engine_kernel<16>;
+    case 1: return cae_engine_kernel<1, MID, TRACE>;
+    case 2: return cae_engine_kernel<2, MID, TRACE>;
+    case 4: return cae_engine_kernel<4, MID, TRACE>;
+    case 8: return cae_engine_kernel<8, MID, TRACE>;
+    default: return cae_engine_kernel<16, MID, TRACE>;
     }
+}
+
+// The instantiation for the largest book, with mid-price code only when some market uses that
+// model and trace stores only for cae_step_traced.
+EngineFn engine_fn(uint32_t tpl_max, bool mid, bool trace)
+{
+    if (mid) return trace ? engine_fn_t<true, true>(tpl_max) : engine_fn_t<true, false>(tpl_max);
+    return trace ? engine_fn_t<false, true>(tpl_max) : engine_fn_t<false, false>(tpl_max);
 }
 
 uint32_t auto_wpm(uint32_t L, uint32_t A)
@@ -1118,6 +1136,7 @@ struct cae_ensemble {
     uint64_t book_words = 0;
     Layout lay{};
     uint32_t n_items = 0, tpl_max = 1, waves_per_group = 1, lds_bytes = 0, grid = 0;
+    bool any_mid = false;  // some market uses the mid-price model
     cae_tuning tuning{};
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     bool have_timing = false;
@@ -1147,6 +1166,7 @@ int build_schedule(cae_ensemble *e, const cae_tuning *tn, const uint32_t *ids,
         t.waves_per_market[c] = (uint8_t)w;
         wpm_max = std::max(wpm_max, w);
         tpl_max = std::max(tpl_max, tpl_for(d.L));
+        e->any_mid |= (d.flags & CAE_MODEL_MASK) == CAE_MODEL_MID;
     }
     uint32_t G = t.waves_per_group;
     if (G == 0) G = std::max(wpm_max, 4u);
@@ -1251,7 +1271,7 @@ int build_schedule(cae_ensemble *e, const cae_tuning *tn, const uint32_t *ids,
     int rc = device_cus(e->device, &ncu);
     if (rc) return rc;
     int per_cu = 0;
-    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(engine_fn(tpl_max)),
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(engine_fn(tpl_max, e->any_mid, false)),
                                                          (int)(G * 64u), (size_t)lds_max));
     if (per_cu < 1) return fail(CAE_EINVAL, "schedule does not fit on a CU (lds %u B, %u waves)", lds_max, G);
     if (t.groups_per_cu) per_cu = std::min<int>(per_cu, (int)t.groups_per_cu);
@@ -1404,7 +1424,7 @@ static int step_impl(cae_ensemble *e, uint32_t S, bool naive, uint32_t *tr_price
     if (naive)
         hipLaunchKernelGGL(cae_naive_kernel, dim3((e->M + 63u) / 64u), dim3(64), 0, e->stream, a, e->M);
     else
-        hipLaunchKernelGGL(engine_fn(e->tpl_max), dim3(e->grid), dim3(e->waves_per_group * 64u), e->lds_bytes,
+        hipLaunchKernelGGL(engine_fn(e->tpl_max, e->any_mid, tr_price != nullptr || tr_vol != nullptr), dim3(e->grid), dim3(e->waves_per_group * 64u), e->lds_bytes,
                            e->stream, a);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipEventRecord(e->ev1, e->stream));
