@@ -574,7 +574,11 @@ __device__ __forceinline__ void run_market(const EngineArgs &args, const Item &i
         else wave_sync();
         ClearOut co;
         if (active && w_in == (i & wpm_mask)) {
+            // the clearing is a chain of dependent scans and reductions that the market's other
+            // waves wait for; top issue priority lets it run ahead of other markets' generation
+            __builtin_amdgcn_s_setprio(3);
             co = clear_dispatch<TPL_MAX>(bk, d.tpl, lane);
+            __builtin_amdgcn_s_setprio(0);
             if constexpr (MULTI) {
                 if (lane == 0) *reinterpret_cast<uint4 *>(scr) = make_uint4(co.p, co.v, co.bb, co.ba);
             }
@@ -724,7 +728,9 @@ __device__ __forceinline__ void run_pair(const EngineArgs &args, const Item &ite
                 uint32_t *bk = lds + Y * item.stride;
                 uint32_t *scr = bk + item.stride - kScr;
                 const DevMarket &dy = Y ? dB : dA;
+                __builtin_amdgcn_s_setprio(3);
                 const ClearOut co = clear_dispatch<TPL_MAX>(bk, dy.tpl, lane);
+                __builtin_amdgcn_s_setprio(0);
                 const uint4 s0 = *reinterpret_cast<const uint4 *>(scr);       // last, prev, steps
                 const uint4 s1 = *reinterpret_cast<const uint4 *>(scr + 4);   // n_trade, sum_vol
                 const uint4 s2 = *reinterpret_cast<const uint4 *>(scr + 8);   // sum_px, sum_spread
