@@ -565,6 +565,7 @@ __device__ __forceinline__ void run_market(const EngineArgs &args, const Item &i
         book_ends(bk, d.tpl, lane, bb, ba);
         mid2 = next_mid2(true, bb, ba, last);
     }
+    if constexpr (MID && MULTI) __syncthreads();  // every wave has read the book before orders land
 
     const double *lnT = args.lnT + d.L;  // ln(L + tick)
     for (uint32_t i = 0; i < args.S; ++i) {

@@ -502,3 +502,24 @@ def test_naive_engine_mid_model(p_mkt):
     rst, rbk = O.run(descs, 12, 30)
     _assert_books(descs, bk, rbk)
     _assert_states(st, rst)
+
+
+def test_mid_model_many_launch_starts():
+    """Each launch reads the mid-price reference of its first step from the book before any
+    wave adds orders: many short launches of lock-step mid-price markets equal the oracle."""
+    rng = np.random.default_rng(31)
+    n = 48
+    L = rng.choice([64, 100, 256, 1000, 1024], n)
+    A = rng.integers(200, 3000, n)
+    d = np.zeros(n, W.MARKET_DTYPE)
+    d["L"], d["A"], d["K"], d["Q"] = L, A, np.maximum(1, L // 16), rng.integers(1, 40, n)
+    d["n_noise"] = A // 2
+    d["n_mom"] = A // 3
+    d["h"] = 2
+    d["flags"] = _mid(0.05)
+    for G, wpm in ((16, 4), (8, 2), (4, 4)):
+        tn = {"waves_per_group": G, "waves_per_market": {c: wpm for c in range(40)}}
+        st, bk, _ = _run_gpu(d, 53, [3] * 12 + [5], tuning=tn)
+        rst, rbk = O.run(d, 53, 41)
+        _assert_books(d, bk, rbk)
+        _assert_states(st, rst)
