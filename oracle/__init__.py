@@ -53,6 +53,9 @@ def lib():
         L.orc_philox_batch.argtypes = [u32, P, P, P]
         L.orc_orders.argtypes = [P, u32, u64, u32, u32, u32, P, P, P]
         L.orc_orders_mid.argtypes = [P, u32, u64, u32, u32, u32, P, P, P]
+        L.orc_splitmix64_mix.argtypes = [u64]
+        L.orc_splitmix64_mix.restype = u64
+        L.orc_splitmix_batch.argtypes = [u32, P, P, u64, P]
         L.orc_state_size.restype = u32
         L.orc_market_size.restype = u32
         assert L.orc_state_size() == STATE_DTYPE.itemsize
@@ -90,11 +93,27 @@ def urange(w, n):
 
 
 MODEL_LAST, MODEL_MID = 0, 1
+GEN_PHILOX, GEN_SPLITMIX = 0, 1
 
 
-def model_flags(model=MODEL_LAST, p_mkt16=0):
-    """Descriptor flags: agent model in bits 0-7, P_mkt (units of 2^-16) in bits 16-31."""
-    return (int(p_mkt16) << 16) | int(model)
+def model_flags(model=MODEL_LAST, p_mkt16=0, gen=GEN_PHILOX):
+    """Descriptor flags: agent model in bits 0-7, generator in bits 8-15, P_mkt (units of
+    2^-16) in bits 16-31."""
+    return (int(p_mkt16) << 16) | (int(gen) << 8) | int(model)
+
+
+def splitmix64(x):
+    """The SplitMix64 output function of one 64-bit input."""
+    return int(lib().orc_splitmix64_mix(int(x) & (2**64 - 1)))
+
+
+def splitmix_words(gid, steps, seed):
+    """Words (n, 4) of the SplitMix64 reading for global agent ids gid[n] at steps[n]."""
+    g = np.ascontiguousarray(gid, dtype=np.uint64)
+    st = np.ascontiguousarray(steps, dtype=np.uint32)
+    out = np.zeros((len(g), 4), np.uint32)
+    lib().orc_splitmix_batch(len(g), _p(g), _p(st), int(seed) & (2**64 - 1), _p(out))
+    return out
 
 
 def market(L, A, K, Q, n_noise=None, n_mom=0, h=2, flags=0):

@@ -20,7 +20,9 @@
  * Readings where the paper is silent (each one is listed in the design notes):
  *   - generator: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel Random Numbers: As
  *     Easy as 1, 2, 3", SC'11) instead of the paper's under-specified SplitMix64 hash.
- *     Counter = (absolute step, agent, market, 0), key = (seed low word, seed high word);
+ *     Counter = (absolute step, agent, market, 0), key = (seed low word, seed high word).
+ *     A descriptor may select the paper's SplitMix64 instead, with the coordinate hash read as
+ *     a position in the seeded stream (orc_splitmix_words);
  *   - integer ranges use the exact multiply-high floor(w * n / 2^32) of a 32-bit word w,
  *     which is the paper's 1 + floor(u * q_max) with u = w / 2^32;
  *   - the agents' reference price is the last clearing tick (integer, no rounding step);
@@ -68,6 +70,32 @@ void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
     out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
 }
 
+/* ---------------------------------------------------------------------------------------
+ * SplitMix64 (Steele, Lea and Flood, "Fast splittable pseudorandom number generators",
+ * OOPSLA 2014), the generator the paper names in section III-G.  Its output for a 64-bit input
+ * x: z = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9; z = (z ^ (z >> 27)) * 0x94d049bb133111eb;
+ * z ^ (z >> 31) (the mixing steps printed in section III-G).  The k-th output of the stream
+ * seeded with s mixes s + (k + 1) * 0x9e3779b97f4a7c15.
+ * ------------------------------------------------------------------------------------- */
+uint64_t orc_splitmix64_mix(uint64_t x)
+{
+    uint64_t z = x;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+/* Reading of the paper's coordinate hash(m A + a, s, c, seed): the stream seeded with `seed`,
+ * at position k = gid * 2^34 + s * 4 + c (gid = m A + a, channel c = 0..3), i.e. the mix of
+ * seed + (k + 1) * 0x9e3779b97f4a7c15; each channel's word is the output's high half. */
+void orc_splitmix_words(uint64_t gid, uint32_t s, uint64_t seed, uint32_t w[4])
+{
+    for (uint32_t c = 0; c < 4; ++c) {
+        uint64_t k = (gid << 34) + ((uint64_t)s << 2) + c;
+        w[c] = (uint32_t)(orc_splitmix64_mix(seed + (k + 1u) * 0x9e3779b97f4a7c15ull) >> 32);
+    }
+}
+
 /* floor(w * n / 2^32): a uniform integer in [0, n) from one 32-bit word. */
 uint32_t orc_range(uint32_t w, uint32_t n)
 {
@@ -85,11 +113,26 @@ typedef struct {
     uint32_t n_noise; /* agents [0, n_noise) are NOISE                                      */
     uint32_t n_mom;   /* agents [n_noise, n_noise + n_mom) are MOMENTUM, the rest MAKER     */
     uint32_t h;       /* maker half-spread in ticks                                         */
-    uint32_t flags;   /* bits 0-7: agent model (ORC_MODEL_*); bits 16-31: the probability
-                         P_mkt of a marketable order in units of 2^-16 (mid-price model only) */
+    uint32_t flags;   /* bits 0-7: agent model (ORC_MODEL_*); bits 8-15: generator (ORC_GEN_*);
+                         bits 16-31: the probability P_mkt of a marketable order in units of
+                         2^-16 (mid-price model only) */
 } orc_market;
 
 enum { ORC_MODEL_LAST = 0, ORC_MODEL_MID = 1 };
+enum { ORC_GEN_PHILOX = 0, ORC_GEN_SPLITMIX = 1 };
+
+/* The four words of agent a of market m at absolute step s, from the descriptor's generator. */
+static void orc_agent_words(const orc_market *d, uint32_t m, uint64_t seed, uint32_t a, uint32_t s,
+                            uint32_t w[4])
+{
+    if (((d->flags >> 8) & 0xFFu) == ORC_GEN_SPLITMIX) {
+        orc_splitmix_words((uint64_t)m * d->A + a, s, seed, w);
+    } else {
+        uint32_t ctr[4] = {s, a, m, 0u};
+        uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+        orc_philox4x32_10(ctr, key, w);
+    }
+}
 
 typedef struct {
     uint32_t last;        /* last clearing tick (agents' reference price)                  */
@@ -128,10 +171,8 @@ static uint32_t clamp_tick(int64_t t, uint32_t L)
 void orc_agent_order(const orc_market *d, uint32_t m, uint64_t seed, uint32_t a, uint32_t s,
                      uint32_t last, uint32_t prev, uint32_t *side, uint32_t *tick, uint32_t *qty)
 {
-    uint32_t ctr[4] = {s, a, m, 0u};
-    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
     uint32_t w[4];
-    orc_philox4x32_10(ctr, key, w);
+    orc_agent_words(d, m, seed, a, s, w);
 
     uint32_t coin = (w[0] < 0x80000000u) ? ORC_BUY : ORC_SELL;
     int64_t ref = (int64_t)last;
@@ -175,10 +216,8 @@ void orc_agent_order(const orc_market *d, uint32_t m, uint64_t seed, uint32_t a,
 void orc_agent_order_mid(const orc_market *d, uint32_t m, uint64_t seed, uint32_t a, uint32_t s,
                          double mid, double mid_prev, uint32_t *side, uint32_t *tick, uint32_t *qty)
 {
-    uint32_t ctr[4] = {s, a, m, 0u};
-    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
     uint32_t w[4];
-    orc_philox4x32_10(ctr, key, w);
+    orc_agent_words(d, m, seed, a, s, w);
 
     const double two32 = 4294967296.0;
     uint32_t coin = (w[0] < 0x80000000u) ? ORC_BUY : ORC_SELL;
@@ -329,7 +368,7 @@ int orc_market_run_traced(const orc_market *d, uint32_t m, uint64_t seed, uint32
     if (d->L < 1 || d->L > 1024) return -1;
     if ((d->flags & 0xFFu) > ORC_MODEL_MID) return -1;
     if ((d->flags & 0xFFu) == ORC_MODEL_LAST && (d->flags >> 16) != 0) return -1;
-    if ((d->flags & 0xFF00u) != 0) return -1;
+    if (((d->flags >> 8) & 0xFFu) > ORC_GEN_SPLITMIX) return -1;
     /* Books are 32-bit: every quantity ever added must fit. */
     if (((uint64_t)st->steps_done + S) * (uint64_t)d->A * (uint64_t)d->Q >= (1ull << 32)) return -2;
     double *lnp = (double *)malloc(sizeof(double) * d->L);
@@ -446,6 +485,12 @@ void orc_orders_mid(const orc_market *d, uint32_t m, uint64_t seed, uint32_t s, 
     for (uint32_t a = 0; a < d->A; ++a)
         orc_agent_order_mid(d, m, seed, a, s, 0.5 * (double)mid2, 0.5 * (double)mid2_prev,
                             &side[a], &tick[a], &qty[a]);
+}
+
+/* Generator words of a batch: SplitMix64 for (gid, s) pairs (pins). */
+void orc_splitmix_batch(uint32_t n, const uint64_t *gid, const uint32_t *steps, uint64_t seed, uint32_t *out)
+{
+    for (uint32_t i = 0; i < n; ++i) orc_splitmix_words(gid[i], steps[i], seed, out + 4 * (size_t)i);
 }
 
 uint32_t orc_state_size(void) { return (uint32_t)sizeof(orc_state); }

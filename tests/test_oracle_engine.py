@@ -252,13 +252,19 @@ def test_trace_records_each_step(orc):
     assert np.array_equal(np.hstack([p1, p2]), pr) and np.array_equal(np.hstack([v1, v2]), vo)
 
 
+def _words(orc, d, m, seed, a, s):
+    if (int(d["flags"][0]) >> 8) & 0xFF == orc.GEN_SPLITMIX:
+        return orc.splitmix_words([m * int(d["A"][0]) + a], [s], seed)[0]
+    return orc.philox([s, a, m, 0], [seed & 0xFFFFFFFF, seed >> 32])
+
+
 def _exact_mid_order(orc, d, m, seed, a, s, mid2, mid2_prev):
     """The paper's mid-price agent rules (section III-C) evaluated in exact rationals."""
     from fractions import Fraction as F
     L, K, Q = int(d["L"][0]), int(d["K"][0]), int(d["Q"][0])
     nn, nm, h = int(d["n_noise"][0]), int(d["n_mom"][0]), int(d["h"][0])
     p_mkt = F(int(d["flags"][0]) >> 16, 65536)
-    w = orc.philox([s, a, m, 0], [seed & 0xFFFFFFFF, seed >> 32])
+    w = _words(orc, d, m, seed, a, s)
     u = [F(int(x), 2**32) for x in w]
     mid, mid_prev = F(mid2, 2), F(mid2_prev, 2)
     coin = orc.BUY if u[0] < F(1, 2) else orc.SELL
@@ -328,3 +334,52 @@ def test_model_flags_validated(orc):
         orc.market_run(orc.market(16, 8, 2, 3, flags=orc.model_flags(orc.MODEL_LAST, 5)), 0, 0, 1)
     with pytest.raises(ValueError):
         orc.market_run(orc.market(16, 8, 2, 3, flags=2), 0, 0, 1)
+
+
+def test_splitmix64_known_answers(orc):
+    """The first outputs of the reference SplitMix64 stream from state 0."""
+    import json, os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "splitmix64_state0.json")))
+    for k, v in enumerate(g["outputs"]):
+        assert orc.splitmix64((k + 1) * 0x9E3779B97F4A7C15) == int(v, 16)
+
+
+def test_splitmix_words_are_stream_positions(orc):
+    """Channel c of agent gid at step s is the high half of stream output gid*2^34 + 4s + c;
+    the words are uniform (chi-square over 64 bins)."""
+    seed = 0x1234_5678_9ABC_DEF0
+    gid = np.array([0, 1, 7, 2**20 + 3, 2**29 - 1], np.uint64)
+    st = np.array([0, 5, 2**31, 17, 999], np.uint32)
+    w = orc.splitmix_words(gid, st, seed)
+    for i in range(len(gid)):
+        for c in range(4):
+            k = (int(gid[i]) << 34) + (int(st[i]) << 2) + c
+            assert w[i, c] == orc.splitmix64(seed + (k + 1) * 0x9E3779B97F4A7C15) >> 32
+    n = 40000
+    w = orc.splitmix_words(np.arange(n, dtype=np.uint64), np.full(n, 3, np.uint32), 7)
+    for c in range(4):
+        counts = np.bincount(w[:, c] >> 26, minlength=64)
+        assert stats.chisquare(counts).pvalue > 1e-4
+
+
+@pytest.mark.parametrize("model", ["last", "mid"])
+def test_splitmix_generator_orders(orc, model):
+    """Orders drawn from the SplitMix64 reading follow the same rules: the mid-price model
+    against exact rationals, the last-tick model against the closed-form mapping."""
+    if model == "mid":
+        d = orc.market(128, 300, 8, 17, n_noise=150, n_mom=90, h=2,
+                       flags=orc.model_flags(orc.MODEL_MID, 6554, orc.GEN_SPLITMIX))
+        side, tick, qty = orc.orders_mid(d, 9, 77, 4, 129, 127)
+        for a in range(300):
+            assert (side[a], tick[a], qty[a]) == _exact_mid_order(orc, d, 9, 77, a, 4, 129, 127)
+    else:
+        d = orc.market(128, 300, 8, 17, flags=orc.model_flags(gen=orc.GEN_SPLITMIX))
+        side, tick, qty = orc.orders(d, 9, 77, 4, 64, 64)
+        w = orc.splitmix_words(9 * 300 + np.arange(300, dtype=np.uint64), np.full(300, 4, np.uint32), 77)
+        off = ((w[:, 1].astype(np.uint64) * 17) >> 32).astype(np.int64) - 8
+        np.testing.assert_array_equal(tick, np.clip(64 + off, 0, 127))
+        np.testing.assert_array_equal(side, (w[:, 0] >= 2**31).astype(np.uint32))
+        np.testing.assert_array_equal(qty, 1 + ((w[:, 2].astype(np.uint64) * 17) >> 32))
+    st, bk = orc.market_run(d, 9, 77, 40)
+    st2, bk2 = orc.market_run(d, 9, 78, 40)
+    assert not np.array_equal(bk, bk2)
