@@ -64,18 +64,26 @@ extern "C" {
 #define CAE_EHIP (-4)      /* the HIP runtime reported an error (message has its text)      */
 #define CAE_ESTATE (-5)    /* the handle is not in a state that allows the call             */
 
-/* Agent models (bits 0-7 of cae_market.flags) and the marketable-order probability P_mkt of
- * the mid-price model (bits 16-31, in units of 2^-16: an order is marketable iff
- * w3 < (flags >> 16) << 16). */
+/* Agent models (bits 0-7 of cae_market.flags), the generator (bits 8-15) and the
+ * marketable-order probability P_mkt of the mid-price model (bits 16-31, in units of 2^-16: an
+ * order is marketable iff w3 < (flags >> 16) << 16).
+ * CAE_GEN_SPLITMIX selects the paper's SplitMix64 (section III-G; Steele, Lea and Flood,
+ * OOPSLA 2014) instead of Philox: word c (0..3) of agent a of market m at step s is the high
+ * half of mix(seed + (k + 1) 0x9e3779b97f4a7c15) with k = (m A + a) 2^34 + 4 s + c, where mix is
+ * the output function printed in section III-G (the paper leaves the coordinate hash open;
+ * this reads it as a position in the seeded stream). */
 #define CAE_MODEL_LAST 0u
 #define CAE_MODEL_MID 1u
 #define CAE_MODEL_MASK 0xFFu
+#define CAE_GEN_PHILOX 0u
+#define CAE_GEN_SPLITMIX 1u
+#define CAE_GEN_SHIFT 8
 #define CAE_PMKT_SHIFT 16
 
 /* One market (32 bytes).  Constraints checked by cae_sizes and cae_create:
  *   1 <= L <= 1024, A >= 1, K <= 2^30 (K < 2^20 in the mid-price model), Q >= 1,
  *   A * Q < 2^32, n_noise + n_mom <= A, maker_half_spread < L; flags: model LAST or MID,
- *   bits 8-15 zero, P_mkt zero in the last-tick model. */
+ *   generator PHILOX or SPLITMIX, P_mkt zero in the last-tick model. */
 typedef struct cae_market {
     uint32_t L;                 /* ticks on the price grid                                */
     uint32_t A;                 /* agents                                                 */

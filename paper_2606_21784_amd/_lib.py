@@ -27,8 +27,10 @@ class State(C.Structure):
                 ("ref2", C.c_uint32), ("reserved", C.c_uint32)]
 
 
-# Agent models (descriptor flags bits 0-7) and the position of P_mkt (bits 16-31).
+# Agent models (descriptor flags bits 0-7), generators (bits 8-15) and the position of P_mkt
+# (bits 16-31).
 MODEL_LAST, MODEL_MID, PMKT_SHIFT = 0, 1, 16
+GEN_PHILOX, GEN_SPLITMIX, GEN_SHIFT = 0, 1, 8
 
 
 class Sizes(C.Structure):

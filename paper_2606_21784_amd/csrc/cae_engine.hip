@@ -358,6 +358,47 @@ __device__ __forceinline__ ClearOut clear_dispatch(uint32_t *bk, uint32_t tpl, u
     return clear_wave<1>(bk, lane);
 }
 
+// SplitMix64 words (the generator named in section III-G), for markets that select it: channel
+// c of agent gid = m A + a at step s is the high half of mix(seed + (k + 1) g) with
+// k = gid 2^34 + 4 s + c and g = 0x9e3779b97f4a7c15, i.e. mix(base_c + ((gid g mod 2^32) << 34))
+// with base_c = seed + (4 s + c + 1) g uniform over the step.
+constexpr uint64_t kGamma = 0x9e3779b97f4a7c15ull;
+
+__device__ __forceinline__ uint32_t splitmix_hi(uint64_t x)
+{
+    uint64_t z = x;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return (uint32_t)((z ^ (z >> 31)) >> 32);
+}
+
+struct SplitMixStep {
+    uint64_t base[4];
+    uint32_t gid0;  // m A (mod 2^32)
+
+    __device__ __forceinline__ SplitMixStep(uint32_t s, uint32_t m, uint32_t A, uint64_t seed)
+    {
+#pragma unroll
+        for (uint32_t c = 0; c < 4; ++c) base[c] = seed + (4ull * s + c + 1ull) * kGamma;
+        gid0 = m * A;
+    }
+
+    __device__ __forceinline__ void words4(uint32_t a, uint32_t &w0, uint32_t &w1, uint32_t &w2,
+                                           uint32_t &w3) const
+    {
+        const uint64_t g = (uint64_t)((gid0 + a) * (uint32_t)kGamma) << 34;
+        w0 = splitmix_hi(base[0] + g);
+        w1 = splitmix_hi(base[1] + g);
+        w2 = splitmix_hi(base[2] + g);
+        w3 = splitmix_hi(base[3] + g);
+    }
+};
+
+__device__ __forceinline__ bool uses_splitmix(const DevMarket &d)
+{
+    return ((d.flags >> CAE_GEN_SHIFT) & 0xFFu) == CAE_GEN_SPLITMIX;
+}
+
 // The references the agents of a market read at the start of a step.
 struct Refs {
     uint32_t last, prev;   // last clearing tick, and the one before the previous step
@@ -383,12 +424,12 @@ struct OrderCtx {
     bool mid;
 };
 
-// MID: the code may meet mid-price markets (false compiles the last-tick rules alone).
-template <bool MID>
+// FULL: the code may meet mid-price markets (false compiles the last-tick rules alone).
+template <bool FULL>
 __device__ __forceinline__ OrderCtx order_ctx(const DevMarket &d, uint32_t s, const Refs &r)
 {
     OrderCtx o;
-    o.mid = MID && (d.flags & CAE_MODEL_MASK) == CAE_MODEL_MID;
+    o.mid = FULL && (d.flags & CAE_MODEL_MASK) == CAE_MODEL_MID;
     o.span = 2u * d.K + 1u;
     o.twoK = 2u * d.K;
     o.Q = d.Q;
@@ -443,7 +484,7 @@ __device__ __forceinline__ uint32_t mid_noise_word(const OrderCtx &o, uint32_t w
 }
 
 // MOMENTUM (a < mom_end) or MAKER agent a, either model.
-template <bool MID>
+template <bool FULL>
 __device__ __forceinline__ uint32_t other_word(const OrderCtx &o, uint32_t a, uint32_t w0, uint32_t w3)
 {
     // tick = bid tick + sell x (ask tick - bid tick), written as arithmetic so that the four
@@ -453,39 +494,48 @@ __device__ __forceinline__ uint32_t other_word(const OrderCtx &o, uint32_t a, ui
     const int lo = mom ? o.mom_bid : o.mk_bid;
     const int span = mom ? o.mom_ask - o.mom_bid : o.mk_ask - o.mk_bid;
     int tick = lo + (int)sell * span;
-    if (MID && mom && w3 < o.tmkt) tick = sell ? 0 : o.top;
+    if (FULL && mom && w3 < o.tmkt) tick = sell ? 0 : o.top;
     tick = min(max(tick, 0), o.top);
     return 2u * (uint32_t)tick + sell;
 }
 
 // Every order of one market-step, added into the LDS book (interleaved pairs: word 2*tick+side).
-template <bool MID>
-__device__ __forceinline__ void gen_orders(const DevMarket &d, uint32_t m, uint32_t s, const Refs &r,
-                                           uint32_t key0, uint32_t key1, uint32_t t, uint32_t nthr,
-                                           uint32_t *bk)
+template <bool FULL, typename Gen>
+__device__ __forceinline__ void gen_with(const DevMarket &d, const OrderCtx &o, const Gen &gen, uint32_t t,
+                                         uint32_t nthr, uint32_t *bk)
 {
-    const PhiloxStep ph(s, m, key0, key1);
-    const OrderCtx o = order_ctx<MID>(d, s, r);
     uint32_t a = t;
-    if (MID && o.mid) {
+    if (FULL && o.mid) {
         for (; a < d.n_noise; a += nthr) {
             uint32_t w0, w1, w2, w3;
-            ph.words4(a, w0, w1, w2, w3);
+            gen.words4(a, w0, w1, w2, w3);
             atomicAdd(&bk[mid_noise_word(o, w0, w1, w3)], order_qty(o, w2));
         }
     } else {
         for (; a < d.n_noise; a += nthr) {
-            uint32_t w0, w1, w2;
-            ph.words(a, w0, w1, w2);
+            uint32_t w0, w1, w2, w3;
+            gen.words4(a, w0, w1, w2, w3);
             atomicAdd(&bk[noise_word(o, w0, w1)], order_qty(o, w2));
         }
     }
     for (; a < d.A; a += nthr) {
         uint32_t w0, w1, w2, w3 = 0;
-        if constexpr (MID) ph.words4(a, w0, w1, w2, w3);
-        else ph.words(a, w0, w1, w2);
-        atomicAdd(&bk[other_word<MID>(o, a, w0, w3)], order_qty(o, w2));
+        gen.words4(a, w0, w1, w2, w3);
+        atomicAdd(&bk[other_word<FULL>(o, a, w0, w3)], order_qty(o, w2));
     }
+}
+
+template <bool FULL>
+__device__ __forceinline__ void gen_orders(const DevMarket &d, uint32_t m, uint32_t s, const Refs &r,
+                                           uint32_t key0, uint32_t key1, uint32_t t, uint32_t nthr,
+                                           uint32_t *bk)
+{
+    const OrderCtx o = order_ctx<FULL>(d, s, r);
+    if (FULL && uses_splitmix(d)) {
+        gen_with<FULL>(d, o, SplitMixStep(s, m, d.A, ((uint64_t)key1 << 32) | key0), t, nthr, bk);
+        return;
+    }
+    gen_with<FULL>(d, o, PhiloxStep(s, m, key0, key1), t, nthr, bk);
 }
 
 // Best bid / best ask (kNone when a side is empty) of an LDS book, by one wave: the reference
@@ -514,7 +564,7 @@ __device__ __forceinline__ uint32_t next_mid2(bool mid, uint32_t bb, uint32_t ba
 
 // One market (or an idle slot of a lock-step item) for all S steps.  MULTI: the market spans
 // several waves and the workgroup barrier separates the phases (Algorithm 1's barriers).
-template <int TPL_MAX, bool MULTI, bool MID, bool TRACE>
+template <int TPL_MAX, bool MULTI, bool FULL, bool TRACE>
 __device__ __forceinline__ void run_market(const EngineArgs &args, const Item &item, uint32_t sub,
                                            uint32_t w_in, uint32_t lane, bool active,
                                            uint32_t *lds)
@@ -558,19 +608,19 @@ __device__ __forceinline__ void run_market(const EngineArgs &args, const Item &i
     }
     if constexpr (MULTI) __syncthreads();
     else wave_sync();
-    const bool mid = MID && (d.flags & CAE_MODEL_MASK) == CAE_MODEL_MID;
+    const bool mid = FULL && (d.flags & CAE_MODEL_MASK) == CAE_MODEL_MID;
     mid2 = 2u * last;
-    if (MID && active && mid) {
+    if (FULL && active && mid) {
         uint32_t bb, ba;
         book_ends(bk, d.tpl, lane, bb, ba);
         mid2 = next_mid2(true, bb, ba, last);
     }
-    if constexpr (MID && MULTI) __syncthreads();  // every wave has read the book before orders land
+    if constexpr (FULL && MULTI) __syncthreads();  // every wave has read the book before orders land
 
     const double *lnT = args.lnT + d.L;  // ln(L + tick)
     for (uint32_t i = 0; i < args.S; ++i) {
         const uint32_t s = (uint32_t)steps0 + i;
-        if (active) gen_orders<MID>(d, d.id, s, Refs{last, prev, mid2, mid2p}, args.k0, args.k1, t, nthr, bk);
+        if (active) gen_orders<FULL>(d, d.id, s, Refs{last, prev, mid2, mid2p}, args.k0, args.k1, t, nthr, bk);
         if constexpr (MULTI) __syncthreads();
         else wave_sync();
         ClearOut co;
@@ -662,7 +712,7 @@ __device__ __forceinline__ void st_u64(uint32_t *p, uint64_t v)
 // G-1 waves generate and aggregate the other market's orders.  One barrier per phase; no wave
 // waits for a clearing.  With one market the phases alternate between its orders and its
 // clearing.  Phase count: 2S (+1 to clear B's last step).
-template <int TPL_MAX, bool MID, bool TRACE>
+template <int TPL_MAX, bool FULL, bool TRACE>
 __device__ __forceinline__ void run_pair(const EngineArgs &args, const Item &item, uint32_t wave, uint32_t lane,
                                          uint32_t G, uint32_t *lds)
 {
@@ -708,7 +758,7 @@ __device__ __forceinline__ void run_pair(const EngineArgs &args, const Item &ite
             uint32_t *scr = bk + item.stride - kScr;
             const uint32_t last = (uint32_t)__builtin_amdgcn_readfirstlane((int)scr[0]);
             uint32_t mid2 = 2u * last;
-            if (MID && (dm.flags & CAE_MODEL_MASK) == CAE_MODEL_MID) {
+            if (FULL && (dm.flags & CAE_MODEL_MASK) == CAE_MODEL_MID) {
                 uint32_t bb, ba;
                 book_ends(bk, dm.tpl, lane, bb, ba);
                 mid2 = next_mid2(true, bb, ba, last);
@@ -763,7 +813,7 @@ __device__ __forceinline__ void run_pair(const EngineArgs &args, const Item &ite
                 }
                 const uint32_t mid2_used = (uint32_t)__builtin_amdgcn_readfirstlane((int)scr[20]);
                 const uint32_t mid2_next =
-                    next_mid2(MID && (dy.flags & CAE_MODEL_MASK) == CAE_MODEL_MID, co.bb, co.ba, last);
+                    next_mid2(FULL && (dy.flags & CAE_MODEL_MASK) == CAE_MODEL_MID, co.bb, co.ba, last);
                 if (lane == 0) {
                     scr[18] = mid2_used;
                     scr[20] = mid2_next;
@@ -786,12 +836,12 @@ __device__ __forceinline__ void run_pair(const EngineArgs &args, const Item &ite
             const uint32_t s = (uint32_t)__builtin_amdgcn_readfirstlane((int)s0.z) + (p >> 1);
             const DevMarket &dx = X ? dB : dA;
             Refs r{last, prev, 0u, 0u};
-            if (MID && (dx.flags & CAE_MODEL_MASK) == CAE_MODEL_MID) {
+            if (FULL && (dx.flags & CAE_MODEL_MASK) == CAE_MODEL_MID) {
                 const uint32_t *scr = bk + item.stride - kScr;
                 r.mid2p = (uint32_t)__builtin_amdgcn_readfirstlane((int)scr[18]);
                 r.mid2 = (uint32_t)__builtin_amdgcn_readfirstlane((int)scr[20]);
             }
-            gen_orders<MID>(dx, dx.id, s, r, args.k0, args.k1, (gidx << 6) | lane, (G - 1u) << 6, bk);
+            gen_orders<FULL>(dx, dx.id, s, r, args.k0, args.k1, (gidx << 6) | lane, (G - 1u) << 6, bk);
         }
         __syncthreads();
         gidx = gidx == 0u ? G - 1u : gidx - 1u;
@@ -816,9 +866,9 @@ __device__ __forceinline__ void run_pair(const EngineArgs &args, const Item &ite
     }
 }
 
-// MID: some market may use the mid-price model; TRACE: record the per-step series.  Each
+// FULL: some market may use the mid-price model; TRACE: record the per-step series.  Each
 // instantiation carries only the code it needs, which keeps scalar registers for the step loop.
-template <int TPL_MAX, bool MID, bool TRACE>
+template <int TPL_MAX, bool FULL, bool TRACE>
 __global__ void __launch_bounds__(1024) cae_engine_kernel(const EngineArgs args)
 {
     extern __shared__ __align__(16) uint32_t lds[];
@@ -839,11 +889,11 @@ __global__ void __launch_bounds__(1024) cae_engine_kernel(const EngineArgs args)
         const uint32_t w_in = wave & ((1u << item.wpm_log2) - 1u);
         const bool active = sub < item.count;
         if (item.pipe) {
-            run_pair<TPL_MAX, MID, TRACE>(args, item, wave, lane, blockDim.x >> 6, lds);
+            run_pair<TPL_MAX, FULL, TRACE>(args, item, wave, lane, blockDim.x >> 6, lds);
         } else if (item.wpm_log2 == 0) {
-            if (active) run_market<TPL_MAX, false, MID, TRACE>(args, item, sub, w_in, lane, true, lds);
+            if (active) run_market<TPL_MAX, false, FULL, TRACE>(args, item, sub, w_in, lane, true, lds);
         } else {
-            run_market<TPL_MAX, true, MID, TRACE>(args, item, sub, w_in, lane, active, lds);
+            run_market<TPL_MAX, true, FULL, TRACE>(args, item, sub, w_in, lane, active, lds);
         }
         __syncthreads();
     }
@@ -883,10 +933,13 @@ __global__ void __launch_bounds__(64) cae_naive_kernel(const EngineArgs args, ui
     for (uint32_t i = 0; i < args.S; ++i) {
         const uint32_t s = (uint32_t)st.steps_done + i;
         const PhiloxStep ph(s, d.id, args.k0, args.k1);
+        const SplitMixStep sm(s, d.id, d.A, ((uint64_t)args.k1 << 32) | args.k0);
+        const bool smx = uses_splitmix(d);
         const OrderCtx o = order_ctx<true>(d, s, Refs{st.last, st.prev, mid2, mid2p});
         for (uint32_t a = 0; a < d.A; ++a) {
             uint32_t w0, w1, w2, w3;
-            ph.words4(a, w0, w1, w2, w3);
+            if (smx) sm.words4(a, w0, w1, w2, w3);
+            else ph.words4(a, w0, w1, w2, w3);
             const uint32_t w = a >= d.n_noise ? other_word<true>(o, a, w0, w3)
                                : mid          ? mid_noise_word(o, w0, w1, w3)
                                               : noise_word(o, w0, w1);
@@ -1060,7 +1113,9 @@ int validate(const cae_market *desc, uint32_t M)
         const uint32_t model = d.flags & CAE_MODEL_MASK;
         if (model != CAE_MODEL_LAST && model != CAE_MODEL_MID)
             return fail(CAE_EINVAL, "market %u: unknown agent model %u", m, model);
-        if ((d.flags & 0xFF00u) != 0) return fail(CAE_EINVAL, "market %u: flags bits 8-15 must be 0", m);
+        const uint32_t gen = (d.flags >> CAE_GEN_SHIFT) & 0xFFu;
+        if (gen != CAE_GEN_PHILOX && gen != CAE_GEN_SPLITMIX)
+            return fail(CAE_EINVAL, "market %u: unknown generator %u", m, gen);
         if (model == CAE_MODEL_LAST && (d.flags >> CAE_PMKT_SHIFT) != 0)
             return fail(CAE_EINVAL, "market %u: P_mkt needs the mid-price model", m);
         if (model == CAE_MODEL_MID && d.K >= (1u << 20))
@@ -1101,15 +1156,15 @@ int device_cus(int dev, uint32_t *num_cu)
 
 using EngineFn = void (*)(const EngineArgs);
 
-template <bool MID, bool TRACE>
+template <bool FULL, bool TRACE>
 EngineFn engine_fn_t(uint32_t tpl_max)
 {
     switch (tpl_max) {
-    case 1: return cae_engine_kernel<1, MID, TRACE>;
-    case 2: return cae_engine_kernel<2, MID, TRACE>;
-    case 4: return cae_engine_kernel<4, MID, TRACE>;
-    case 8: return cae_engine_kernel<8, MID, TRACE>;
-    default: return cae_engine_kernel<16, MID, TRACE>;
+    case 1: return cae_engine_kernel<1, FULL, TRACE>;
+    case 2: return cae_engine_kernel<2, FULL, TRACE>;
+    case 4: return cae_engine_kernel<4, FULL, TRACE>;
+    case 8: return cae_engine_kernel<8, FULL, TRACE>;
+    default: return cae_engine_kernel<16, FULL, TRACE>;
     }
 }
 
@@ -1143,7 +1198,7 @@ struct cae_ensemble {
     uint64_t book_words = 0;
     Layout lay{};
     uint32_t n_items = 0, tpl_max = 1, waves_per_group = 1, lds_bytes = 0, grid = 0;
-    bool any_mid = false;  // some market uses the mid-price model
+    bool any_mid = false;  // some market uses the mid-price model or the SplitMix64 generator
     cae_tuning tuning{};
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     bool have_timing = false;
@@ -1173,7 +1228,8 @@ int build_schedule(cae_ensemble *e, const cae_tuning *tn, const uint32_t *ids,
         t.waves_per_market[c] = (uint8_t)w;
         wpm_max = std::max(wpm_max, w);
         tpl_max = std::max(tpl_max, tpl_for(d.L));
-        e->any_mid |= (d.flags & CAE_MODEL_MASK) == CAE_MODEL_MID;
+        e->any_mid |= (d.flags & CAE_MODEL_MASK) == CAE_MODEL_MID ||
+                      ((d.flags >> CAE_GEN_SHIFT) & 0xFFu) == CAE_GEN_SPLITMIX;
     }
     uint32_t G = t.waves_per_group;
     if (G == 0) G = std::max(wpm_max, 4u);

@@ -28,15 +28,18 @@ def _p(a):
     return a.ctypes.data_as(C.c_void_p)
 
 
-def model_flags(model=_lib.MODEL_LAST, p_mkt=0.0):
-    """Descriptor flags for an agent model (MODEL_LAST / MODEL_MID) and, for the mid-price
-    model, the marketable-order probability P_mkt (rounded to a multiple of 2^-16)."""
+def model_flags(model=_lib.MODEL_LAST, p_mkt=0.0, gen=_lib.GEN_PHILOX):
+    """Descriptor flags for an agent model (MODEL_LAST / MODEL_MID), the generator
+    (GEN_PHILOX / GEN_SPLITMIX) and, for the mid-price model, the marketable-order probability
+    P_mkt (rounded to a multiple of 2^-16)."""
     p16 = int(round(float(p_mkt) * 65536))
     if not 0 <= p16 < 65536:
         raise ValueError("P_mkt must lie in [0, 1)")
     if p16 and model != _lib.MODEL_MID:
         raise ValueError("P_mkt needs the mid-price model")
-    return (p16 << _lib.PMKT_SHIFT) | int(model)
+    if gen not in (_lib.GEN_PHILOX, _lib.GEN_SPLITMIX):
+        raise ValueError("unknown generator")
+    return (p16 << _lib.PMKT_SHIFT) | (int(gen) << _lib.GEN_SHIFT) | int(model)
 
 
 def markets(L, A, K, Q, M=1, n_noise=None, n_mom=0, h=2, flags=0):

@@ -65,8 +65,8 @@ def test_sizes(cae):
 
 @pytest.mark.parametrize("field,value", [("L", 0), ("L", 1025), ("A", 0), ("Q", 0),
                                          ("K", 2**30 + 1), ("n_noise", 11), ("h", 64),
-                                         ("flags", 2), ("flags", 0x100), ("flags", 5 << 16),
-                                         ("flags", 1 | (1 << 8))])
+                                         ("flags", 2), ("flags", 0x200), ("flags", 5 << 16),
+                                         ("flags", 1 | (2 << 8))])
 def test_invalid_descriptors(cae, field, value):
     from paper_2606_21784_amd import engine
     d = engine.markets(64, 10, 4, 5, M=3)
@@ -88,6 +88,9 @@ def test_mid_model_descriptors(cae):
         _sizes(bad)
     with pytest.raises(ValueError):
         engine.model_flags(cae.MODEL_LAST, 0.1)
+    sm = engine.markets(64, 10, 4, 5, M=2, flags=engine.model_flags(gen=cae.GEN_SPLITMIX))
+    assert int(sm["flags"][0]) == 1 << 8
+    _sizes(sm)
 
 
 def test_agents_times_quantity_guard(cae):

@@ -523,3 +523,44 @@ def test_mid_model_many_launch_starts():
         rst, rbk = O.run(d, 53, 41)
         _assert_books(d, bk, rbk)
         _assert_states(st, rst)
+
+
+@pytest.mark.parametrize("mode", ["lockstep", "single", "pipelined"])
+@pytest.mark.parametrize("model", ["last", "mid"])
+def test_splitmix_generator_matches_oracle(mode, model):
+    """Markets that select the SplitMix64 generator (section III-G) give the oracle's books,
+    states and traces in every schedule mode, next to Philox markets in the same launch."""
+    E = _engine()
+    flags = (O.model_flags(O.MODEL_MID, 3277, O.GEN_SPLITMIX) if model == "mid"
+             else O.model_flags(gen=O.GEN_SPLITMIX))
+    descs = W.uniform(10, 100, 300, 9, 20, n_noise=150, n_mom=90, h=3, flags=flags)
+    descs["flags"][::3] = 0  # some Philox markets in the same launch
+    tn = {"lockstep": {"waves_per_group": 4, "waves_per_market": {c: 2 for c in range(40)}},
+          "single": {"waves_per_group": 4, "waves_per_market": {c: 1 for c in range(40)}},
+          "pipelined": {"waves_per_group": 4, "pipelined": {c: 1 for c in range(40)}}}[mode]
+    ens = E.Ensemble(descs, 0xDEADBEEF12345, tuning=tn, market_ids=np.arange(10) * 7 + 3)
+    ens.step(11)
+    pr, vo = ens.step_traced(20)
+    st, bk = ens.read_state(), ens.read_books()
+    ens.close()
+    rst, rbk = O.run(descs, 0xDEADBEEF12345, 11, ids=np.arange(10) * 7 + 3)
+    rst, rbk, rpr, rvo = O.run(descs, 0xDEADBEEF12345, 20, ids=np.arange(10) * 7 + 3, states=rst,
+                               book=rbk, trace=True)
+    _assert_books(descs, bk, rbk)
+    _assert_states(st, rst)
+    np.testing.assert_array_equal(_u32(pr), rpr)
+    np.testing.assert_array_equal(_u32(vo), rvo.astype(np.uint32))
+
+
+def test_naive_engine_splitmix():
+    E = _engine()
+    descs = W.uniform(40, 64, 200, 4, 9, n_noise=120, n_mom=40, h=2,
+                      flags=O.model_flags(O.MODEL_MID, 1000, O.GEN_SPLITMIX))
+    ens = E.Ensemble(descs, 99)
+    ens.step_naive(7)
+    ens.step(6)
+    st, bk = ens.read_state(), ens.read_books()
+    ens.close()
+    rst, rbk = O.run(descs, 99, 13)
+    _assert_books(descs, bk, rbk)
+    _assert_states(st, rst)
