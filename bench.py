@@ -374,7 +374,7 @@ def main():
     traffic = measured_traffic()
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12,
             "unit": "Tslot/s", "frac": achieved / PEAK_SLOTS, "traffic": traffic,
-            "kernel": "cae_engine_kernel<4>", "kernel_ms": kms,
+            "kernel": "cae_engine_kernel<%d, false, false>" % max(1, L // 64), "kernel_ms": kms,
             "slots_per_event": w_ev, "events_per_launch": events,
             "roofline_events_per_s": PEAK_SLOTS / w_ev}
 
