@@ -252,12 +252,79 @@ __device__ __forceinline__ void store_pairs(uint32_t *bk, uint32_t q, const uint
     }
 }
 
+// Clearing of a book of at most 4 ticks per lane, its ticks held in registers throughout: the
+// demand D and supply S of every tick are formed once, the volume pass and the fill reuse them,
+// and the fill takes running minima with V*: fill_b(q) = min(D(q), V*) - min(D(q+1), V*),
+// fill_s(q) = min(S(q), V*) - min(S(q-1), V*).  Every instruction here is on the step's critical
+// path (one wave, the rest of the market waiting), so the pass is kept short.
+template <int TPL>
+__device__ __forceinline__ ClearOut clear_small(uint32_t *__restrict__ bk, uint32_t lane)
+{
+    const uint32_t q0 = lane * TPL;
+    uint32_t b[TPL], k[TPL];
+    load_pairs<TPL>(bk, q0, b, k);
+    uint32_t sb = 0, sa = 0;
+#pragma unroll
+    for (int j = 0; j < TPL; ++j) {
+        sb += b[j];
+        sa += k[j];
+    }
+    uint32_t ib = sb, ia = sa;
+    wave_scan_add2(ib, ia);
+    const uint32_t Tb = readlane(ib, 63);
+    uint32_t D[TPL + 1], Sq[TPL];  // D(q0 + j), S(q0 + j); D[TPL] = D(q0 + TPL)
+    D[0] = Tb - (ib - sb);
+    const uint32_t Sb = ia - sa;   // asks below this lane's first tick
+#pragma unroll
+    for (int j = 0; j < TPL; ++j) {
+        D[j + 1] = D[j] - b[j];
+        Sq[j] = (j ? Sq[j - 1] : Sb) + k[j];
+    }
+    uint32_t best = min(D[0], Sq[0]), bj = 0;
+#pragma unroll
+    for (int j = 1; j < TPL; ++j) {
+        const uint32_t V = min(D[j], Sq[j]);
+        if (V > best) {
+            best = V;
+            bj = (uint32_t)j;
+        }
+    }
+    ClearOut out;
+    out.v = wave_max(best);
+    out.p = 0;
+    if (out.v != 0) out.p = readlane(q0 + bj, (uint32_t)__builtin_ctzll(ballot(best == out.v)));
+    const uint32_t vs = out.v;
+    uint32_t md = min(D[0], vs), ms = min(Sb, vs);
+#pragma unroll
+    for (int j = 0; j < TPL; ++j) {
+        const uint32_t md1 = min(D[j + 1], vs), ms1 = min(Sq[j], vs);
+        b[j] -= md - md1;
+        k[j] -= ms1 - ms;
+        md = md1;
+        ms = ms1;
+    }
+    store_pairs<TPL>(bk, q0, b, k);
+    uint32_t hb = kNone, la = kNone;
+#pragma unroll
+    for (int j = 0; j < TPL; ++j)
+        if (b[j] != 0) hb = q0 + j;
+#pragma unroll
+    for (int j = TPL - 1; j >= 0; --j)
+        if (k[j] != 0) la = q0 + j;
+    const uint64_t mb = ballot(hb != kNone);
+    const uint64_t ma = ballot(la != kNone);
+    out.bb = mb ? readlane(hb, 63u - (uint32_t)__builtin_clzll(mb)) : kNone;
+    out.ba = ma ? readlane(la, (uint32_t)__builtin_ctzll(ma)) : kNone;
+    return out;
+}
+
 // Clears one book with one wave.  bk: LDS pairs (bid, ask) for ticks [0, 64*TPL), zero beyond L.
 // Lane l owns ticks [l*TPL, l*TPL + TPL) and streams them from LDS in chunks of at most four
 // ticks per pass (sums; volumes; fill), so registers do not grow with L.  Wave-uniform result.
 template <int TPL>
 __device__ __forceinline__ ClearOut clear_wave(uint32_t *__restrict__ bk, uint32_t lane)
 {
+    if constexpr (TPL <= 4) return clear_small<TPL>(bk, lane);
     constexpr int CH = TPL < 4 ? TPL : 4;
     constexpr int NCH = TPL / CH;
     const uint32_t q0 = lane * TPL;
