@@ -631,6 +631,37 @@ __device__ __forceinline__ uint32_t next_mid2(bool mid, uint32_t bb, uint32_t ba
 
 // One market (or an idle slot of a lock-step item) for all S steps.  MULTI: the market spans
 // several waves and the workgroup barrier separates the phases (Algorithm 1's barriers).
+// Lock-step markets keep their statistics in LDS scratch words 8..21 (n_trade, sum_vol,
+// sum_px, sum_spread, n_spread, sum_r, sum_r2) and the clearing result of step i in words
+// 4 (i & 1) .. 4 (i & 1) + 3.  A step's statistics are added during the next step's clearing by
+// a wave that would otherwise wait for it, in step order.  last / prev: the prices after the
+// step whose result `cob` holds.
+__device__ __forceinline__ void stats_to_lds(uint32_t *scr, const uint32_t *cob, uint32_t last, uint32_t prev,
+                                             const double *lnT, uint32_t lane)
+{
+    const uint4 r = *reinterpret_cast<const uint4 *>(cob);
+    const uint32_t p = (uint32_t)__builtin_amdgcn_readfirstlane((int)r.x);
+    const uint32_t v = (uint32_t)__builtin_amdgcn_readfirstlane((int)r.y);
+    const uint32_t bb = (uint32_t)__builtin_amdgcn_readfirstlane((int)r.z);
+    const uint32_t ba = (uint32_t)__builtin_amdgcn_readfirstlane((int)r.w);
+    const double x = lnT[last] - lnT[prev];
+    if (lane == 0) {
+        uint64_t *a = reinterpret_cast<uint64_t *>(scr + 8);
+        double *f = reinterpret_cast<double *>(scr + 18);
+        if (v != 0) {
+            a[0] += 1;
+            a[1] += v;
+            a[2] += p;
+        }
+        if (bb != kNone && ba != kNone) {
+            a[3] += (uint64_t)(ba - bb);
+            a[4] += 1;
+        }
+        f[0] = f[0] + x;
+        f[1] = f[1] + x * x;
+    }
+}
+
 template <int TPL_MAX, bool MULTI, bool FULL, bool TRACE>
 __device__ __forceinline__ void run_market(const EngineArgs &args, const Item &item, uint32_t sub,
                                            uint32_t w_in, uint32_t lane, bool active,
@@ -662,6 +693,9 @@ __device__ __forceinline__ void run_market(const EngineArgs &args, const Item &i
         sum_r = st->sum_r;
         sum_r2 = st->sum_r2;
         mid2p = st->ref2;
+        if constexpr (MULTI) {
+            if (t < 14u) scr[8u + t] = reinterpret_cast<const uint32_t *>(st)[4u + t];  // n_trade .. sum_r2
+        }
         const uint32_t *gb = args.book + d.book_off;
         const uint32_t padded = 64u * d.tpl;
         for (uint32_t q = t; q < padded; q += nthr) {
@@ -691,45 +725,67 @@ __device__ __forceinline__ void run_market(const EngineArgs &args, const Item &i
         if constexpr (MULTI) __syncthreads();
         else wave_sync();
         ClearOut co;
-        if (active && w_in == (i & wpm_mask)) {
+        const uint32_t c = i & wpm_mask;
+        if (active && w_in == c) {
             // the clearing is a chain of dependent scans and reductions that the market's other
             // waves wait for; top issue priority lets it run ahead of other markets' generation
             __builtin_amdgcn_s_setprio(3);
             co = clear_dispatch<TPL_MAX>(bk, d.tpl, lane);
             __builtin_amdgcn_s_setprio(0);
             if constexpr (MULTI) {
-                if (lane == 0) *reinterpret_cast<uint4 *>(scr) = make_uint4(co.p, co.v, co.bb, co.ba);
+                if (lane == 0)
+                    *reinterpret_cast<uint4 *>(scr + 4u * (i & 1u)) = make_uint4(co.p, co.v, co.bb, co.ba);
             }
+        } else if (MULTI && active && i >= 1u && w_in == ((c + 1u) & wpm_mask)) {
+            stats_to_lds(scr, scr + 4u * ((i - 1u) & 1u), last, prev, lnT, lane);  // the previous step's
         }
         if constexpr (MULTI) __syncthreads();
         else wave_sync();
         if (active) {
             if constexpr (MULTI) {
-                const uint4 r = *reinterpret_cast<const uint4 *>(scr);
+                const uint4 r = *reinterpret_cast<const uint4 *>(scr + 4u * (i & 1u));
                 co.p = (uint32_t)__builtin_amdgcn_readfirstlane((int)r.x);
                 co.v = (uint32_t)__builtin_amdgcn_readfirstlane((int)r.y);
                 co.bb = (uint32_t)__builtin_amdgcn_readfirstlane((int)r.z);
                 co.ba = (uint32_t)__builtin_amdgcn_readfirstlane((int)r.w);
             }
             prev = last;
-            if (co.v != 0) {
-                last = co.p;
-                n_trade += 1;
-                sum_vol += co.v;
-                sum_px += co.p;
-            }
-            if (co.bb != kNone && co.ba != kNone) {
-                sum_spread += (uint64_t)(co.ba - co.bb);
-                n_spread += 1;
+            if (co.v != 0) last = co.p;
+            if constexpr (!MULTI) {
+                if (co.v != 0) {
+                    n_trade += 1;
+                    sum_vol += co.v;
+                    sum_px += co.p;
+                }
+                if (co.bb != kNone && co.ba != kNone) {
+                    sum_spread += (uint64_t)(co.ba - co.bb);
+                    n_spread += 1;
+                }
+                const double r = lnT[last] - lnT[prev];
+                sum_r = sum_r + r;
+                sum_r2 = sum_r2 + r * r;
             }
             mid2p = mid2;
             mid2 = next_mid2(mid, co.bb, co.ba, last);
-            const double r = lnT[last] - lnT[prev];
-            sum_r = sum_r + r;
-            sum_r2 = sum_r2 + r * r;
             if constexpr (TRACE) {
                 if (t == 0) trace_step(args, m, i, last, co.v);
             }
+        }
+    }
+    if constexpr (MULTI) {
+        // the last step's statistics; then wave 0 holds the totals of every step
+        if (active && w_in == 0u && args.S >= 1u) {
+            stats_to_lds(scr, scr + 4u * ((args.S - 1u) & 1u), last, prev, lnT, lane);
+            wave_sync();
+            const uint64_t *a = reinterpret_cast<const uint64_t *>(scr + 8);
+            const double *f = reinterpret_cast<const double *>(scr + 18);
+            n_trade = a[0];
+            sum_vol = a[1];
+            sum_px = a[2];
+            sum_spread = a[3];
+            n_spread = a[4];
+            sum_r = f[0];
+            sum_r2 = f[1];
         }
     }
     if (active) {
