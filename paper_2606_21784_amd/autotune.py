@@ -25,6 +25,9 @@ from . import engine
 WPM_CANDIDATES = (1, 2, 4, 8, 16)
 PIPE_GROUPS = (4, 8)
 GROUP_CANDIDATES = (4, 8, 16)
+# A candidate within this fraction of the fastest counts as a tie; ties go to the schedule
+# with fewer waves per market, which leaves the whole ensemble more freedom of group size.
+TIE = 0.02
 
 
 def classes_of(descs):
@@ -78,16 +81,18 @@ def tune(descs, seed=0, S_probe=None, min_markets=None, cache=None, arch="gfx950
     """Return a tuning dict for ``engine.Ensemble(..., tuning=...)``.
 
     descs: the ensemble's market descriptors; S_probe: steps per timed probe launch (default:
-    sized by probe_steps); min_markets: markets per class probe (default 4 per CU); cache:
-    optional JSON path.
+    sized by probe_steps); min_markets: fewest markets in a class probe (default 4 per CU; a
+    probe holds the class's own markets, at most 32 per CU, so that it sees the occupancy the
+    ensemble will have); cache: optional JSON path.
     """
     rng = np.random.default_rng(0)
     cached = {}
     if cache and os.path.exists(cache):
         with open(cache) as f:
             cached = json.load(f).get(arch, {})
+    ncu = engine.device_info()["num_cu"]
     if min_markets is None:
-        min_markets = 4 * engine.device_info()["num_cu"]
+        min_markets = 4 * ncu
     cls = classes_of(descs)
     wpm = {}
     pipe_c = {}
@@ -100,11 +105,16 @@ def tune(descs, seed=0, S_probe=None, min_markets=None, cache=None, arch="gfx950
             pipe_c[c] = bool(cached[key].get("pipelined", False))
             cost[c] = float(cached[key]["ns_per_market_step"])
             continue
-        probe = _probe_set(descs, np.nonzero(cls == c)[0], min_markets, rng)
+        idx = np.nonzero(cls == c)[0]
+        # the class's own markets: a class that is the whole ensemble is probed as it is, a
+        # small class of a mixed ensemble is replicated up to min_markets
+        n = min(len(idx) if len(idx) == len(descs) else max(len(idx), min_markets), 32 * ncu)
+        probe = _probe_set(descs, idx, n, rng)
         Sp = S_probe or probe_steps(probe)
         events = float(probe["A"].astype(np.float64).sum()) * Sp
         cands = [(w, False, max(4, w)) for w in WPM_CANDIDATES] + [(1, True, G) for G in PIPE_GROUPS]
         best = None
+        timings = []
         for w, pipe, G in cands:
             tn = {"waves_per_group": G, "waves_per_market": {int(c): w}}
             if pipe:
@@ -116,25 +126,27 @@ def tune(descs, seed=0, S_probe=None, min_markets=None, cache=None, arch="gfx950
                      ms, events / (ms * 1e-3)))
             if best is None or ms < best[3]:
                 best = (w, pipe, G, ms)
+            timings.append((w, pipe, G, ms))
+        # fewest waves per market among the near-fastest (candidates are in increasing order)
+        best = next(x for x in timings if x[3] <= best[3] * (1.0 + TIE))
         wpm[c] = best[0]
         pipe_c[c] = best[1]
         # per market-step cost when the class fills the GPU alone
-        cost[c] = best[3] * 1e6 / (len(probe) * Sp) * engine.device_info()["num_cu"]
+        cost[c] = best[3] * 1e6 / (len(probe) * Sp) * ncu
         cached[key] = {"waves_per_market": wpm[c], "pipelined": bool(pipe_c[c]),
                        "ns_per_market_step": cost[c]}
-    # waves per workgroup on the whole ensemble
-    wmax = max(wpm.values())
+    # waves per workgroup on the whole ensemble; classes that asked for more waves per market
+    # than a candidate group holds are clamped to it
     best_g = None
     for G in GROUP_CANDIDATES:
-        if G < wmax:
-            continue
-        tn = {"waves_per_group": G, "waves_per_market": {int(c): w for c, w in wpm.items()},
+        tn = {"waves_per_group": G, "waves_per_market": {int(c): min(w, G) for c, w in wpm.items()},
               "pipelined": {int(c): 1 for c, p in pipe_c.items() if p}}
         ms = _time_launch(descs, seed, tn, S_probe or probe_steps(descs))
         if log:
             log("waves_per_group %2d: %.3f ms" % (G, ms))
         if best_g is None or ms < best_g[1]:
             best_g = (G, ms)
+    wpm = {c: min(w, best_g[0]) for c, w in wpm.items()}
     if cache:
         allc = {}
         if os.path.exists(cache):

@@ -673,6 +673,9 @@ __device__ __forceinline__ void run_market(const EngineArgs &args, const Item &i
     uint32_t *bk = lds + sub * item.stride;
     uint32_t *scr = bk + item.stride - kScr;
 
+    // statistics in LDS, added by an idle wave (lock-step markets; the widest books keep them
+    // in registers, where the extra live values would spill)
+    constexpr bool kLazy = MULTI && TPL_MAX <= 8;
     uint32_t m = 0;
     DevMarket d{};
     uint32_t last = 0, prev = 0, mid2 = 0, mid2p = 0;
@@ -693,7 +696,7 @@ __device__ __forceinline__ void run_market(const EngineArgs &args, const Item &i
         sum_r = st->sum_r;
         sum_r2 = st->sum_r2;
         mid2p = st->ref2;
-        if constexpr (MULTI) {
+        if constexpr (kLazy) {
             if (t < 14u) scr[8u + t] = reinterpret_cast<const uint32_t *>(st)[4u + t];  // n_trade .. sum_r2
         }
         const uint32_t *gb = args.book + d.book_off;
@@ -736,7 +739,7 @@ __device__ __forceinline__ void run_market(const EngineArgs &args, const Item &i
                 if (lane == 0)
                     *reinterpret_cast<uint4 *>(scr + 4u * (i & 1u)) = make_uint4(co.p, co.v, co.bb, co.ba);
             }
-        } else if (MULTI && active && i >= 1u && w_in == ((c + 1u) & wpm_mask)) {
+        } else if (kLazy && active && i >= 1u && w_in == ((c + 1u) & wpm_mask)) {
             stats_to_lds(scr, scr + 4u * ((i - 1u) & 1u), last, prev, lnT, lane);  // the previous step's
         }
         if constexpr (MULTI) __syncthreads();
@@ -751,7 +754,7 @@ __device__ __forceinline__ void run_market(const EngineArgs &args, const Item &i
             }
             prev = last;
             if (co.v != 0) last = co.p;
-            if constexpr (!MULTI) {
+            if constexpr (!kLazy) {
                 if (co.v != 0) {
                     n_trade += 1;
                     sum_vol += co.v;
@@ -772,7 +775,7 @@ __device__ __forceinline__ void run_market(const EngineArgs &args, const Item &i
             }
         }
     }
-    if constexpr (MULTI) {
+    if constexpr (kLazy) {
         // the last step's statistics; then wave 0 holds the totals of every step
         if (active && w_in == 0u && args.S >= 1u) {
             stats_to_lds(scr, scr + 4u * ((args.S - 1u) & 1u), last, prev, lnT, lane);
