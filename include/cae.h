@@ -149,6 +149,15 @@ typedef struct cae_tuning {
                                                    market while the others generate the
                                                    other's orders); waves_per_market is then
                                                    ignored.  Needs waves_per_group >= 2.   */
+    uint8_t overlap[CAE_NUM_CLASSES];           /* k >= 1: lock-step markets of this class
+                                                   generate the next step's orders while the
+                                                   current step clears, the clearing wave
+                                                   taking k - 1 rows of 64 agents after its
+                                                   clearing; 0 = off.  Applies to classes of
+                                                   2 or more waves per market, not pipelined,
+                                                   in ensembles of last-tick markets with the
+                                                   Philox generator; ignored (reported as 0)
+                                                   elsewhere.                               */
     float class_cost[CAE_NUM_CLASSES];          /* relative cost of one market-step per
                                                    class for the longest-first order;
                                                    0 = the built-in model A + 2*64*TPL    */

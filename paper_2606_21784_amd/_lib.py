@@ -47,6 +47,7 @@ class Tuning(C.Structure):
                 ("max_lds_bytes", C.c_uint32), ("flags", C.c_uint32),
                 ("waves_per_market", C.c_uint8 * NUM_CLASSES),
                 ("pipelined", C.c_uint8 * NUM_CLASSES),
+                ("overlap", C.c_uint8 * NUM_CLASSES),
                 ("class_cost", C.c_float * NUM_CLASSES)]
 
 

@@ -13,7 +13,10 @@
 //     maximal volume, and the fill uses the closed form
 //        fill_bid(q) = min(D(q), V*) - min(D(q+1), V*),  fill_ask(q) = min(S(q), V*) - min(S(q-1), V*).
 //     No cross-wave scan pass and only two barriers per step; the clearing wave rotates with the
-//     step so the clearing work spreads over the CU's four SIMDs.
+//     step so the clearing work spreads over the CU's four SIMDs.  Optionally (last-tick model)
+//     the other waves generate the NEXT step's orders while the clearing runs, aggregated by
+//     their offset from the not-yet-known reference; the clearing wave adds them to the book
+//     once the price is known: one barrier per step and no wave waits for a clearing.
 //   * Books are uint32 (exact integers; a host-side guard proves no overflow), stored in LDS as
 //     interleaved (bid, ask) pairs so the clearing wave reads a tick with one 64-bit access.
 //   * The order generator is Philox4x32-10 with counter (step, agent, market, 0): the first round
@@ -55,7 +58,11 @@ struct Item {
     uint32_t count;     // markets in this item
     uint32_t wpm_log2;  // log2(waves per market) (single-wave or lock-step items)
     uint32_t stride;    // LDS words per market slice (book pairs + kScr scratch words)
-    uint32_t pipe;      // 1: two markets share all the workgroup's waves in alternating phases
+    uint32_t pipe;      // 1: two markets share all the workgroup's waves in alternating phases;
+                        // 2: lock-step with the next step's orders generated during the clearing
+    uint32_t share;     // pipe 2: rows of 64 agents the clearing wave generates after clearing
+    uint32_t hoff;      // pipe 2: word offset of the two order-bin buffers in a market slice
+    uint32_t hwords;    // pipe 2: words per order-bin buffer
 };
 
 constexpr uint32_t kScr = 32;  // scratch words at the end of every market slice
@@ -141,8 +148,22 @@ struct PhiloxStep {
     __device__ __forceinline__ void words4(uint32_t a, uint32_t &w0, uint32_t &w1, uint32_t &w2,
                                            uint32_t &w3) const
     {
+        words4x(ua ^ a, w0, w1, w2, w3);
+    }
+
+    // Agent b | t for a row base b (uniform) and a lane offset t below b's lowest set bit: the
+    // first product's input ua ^ a = (ua ^ b) ^ t, whose uniform half is scalar work.
+    __device__ __forceinline__ void words4_row(uint32_t b, uint32_t t, uint32_t &w0, uint32_t &w1, uint32_t &w2,
+                                               uint32_t &w3) const
+    {
+        words4x((ua ^ b) ^ t, w0, w1, w2, w3);
+    }
+
+    __device__ __forceinline__ void words4x(uint32_t x0, uint32_t &w0, uint32_t &w1, uint32_t &w2,
+                                            uint32_t &w3) const
+    {
         uint32_t h, l;
-        mulhilo(kM0, ua ^ a, h, l);
+        mulhilo(kM0, x0, h, l);
         const uint32_t y2 = h ^ ux3k, y3 = l;
         mulhilo(kM1, y2, h, l);
         uint32_t c0 = h ^ uz0, c1 = l, c2 = uz2 ^ y3, c3 = z3;
@@ -459,6 +480,12 @@ struct SplitMixStep {
         w2 = splitmix_hi(base[2] + g);
         w3 = splitmix_hi(base[3] + g);
     }
+
+    __device__ __forceinline__ void words4_row(uint32_t b, uint32_t t, uint32_t &w0, uint32_t &w1, uint32_t &w2,
+                                               uint32_t &w3) const
+    {
+        words4(b | t, w0, w1, w2, w3);
+    }
 };
 
 __device__ __forceinline__ bool uses_splitmix(const DevMarket &d)
@@ -567,42 +594,136 @@ __device__ __forceinline__ uint32_t other_word(const OrderCtx &o, uint32_t a, ui
 }
 
 // Every order of one market-step, added into the LDS book (interleaved pairs: word 2*tick+side).
-template <bool FULL, typename Gen>
+// Agents run in rows of nthr at uniform bases b: agent b + t for t < nthr.  POW2: nthr is a power
+// of two, so b + t = b | t and the generator folds the uniform half of its input in scalar work.
+template <bool POW2, typename Gen>
+__device__ __forceinline__ void row_words(const Gen &gen, uint32_t b, uint32_t t, uint32_t &w0, uint32_t &w1,
+                                          uint32_t &w2, uint32_t &w3)
+{
+    if constexpr (POW2) gen.words4_row(b, t, w0, w1, w2, w3);
+    else gen.words4(b + t, w0, w1, w2, w3);
+}
+
+template <bool FULL, bool POW2, typename Gen>
 __device__ __forceinline__ void gen_with(const DevMarket &d, const OrderCtx &o, const Gen &gen, uint32_t t,
                                          uint32_t nthr, uint32_t *bk)
 {
-    uint32_t a = t;
+    const uint32_t nn = d.n_noise;
+    uint32_t b = 0;
     if (FULL && o.mid) {
-        for (; a < d.n_noise; a += nthr) {
+        for (; b + nthr <= nn; b += nthr) {
             uint32_t w0, w1, w2, w3;
-            gen.words4(a, w0, w1, w2, w3);
+            row_words<POW2>(gen, b, t, w0, w1, w2, w3);
             atomicAdd(&bk[mid_noise_word(o, w0, w1, w3)], order_qty(o, w2));
         }
     } else {
-        for (; a < d.n_noise; a += nthr) {
-            uint32_t w0, w1, w2, w3;
-            gen.words4(a, w0, w1, w2, w3);
+        // two full rows per pass: two independent generator chains for the wave to issue from
+        for (; b + 2u * nthr <= nn; b += 2u * nthr) {
+            uint32_t w0, w1, w2, w3, x0, x1, x2, x3;
+            row_words<POW2>(gen, b, t, w0, w1, w2, w3);
+            row_words<POW2>(gen, b + nthr, t, x0, x1, x2, x3);
             atomicAdd(&bk[noise_word(o, w0, w1)], order_qty(o, w2));
+            atomicAdd(&bk[noise_word(o, x0, x1)], order_qty(o, x2));
         }
     }
-    for (; a < d.A; a += nthr) {
-        uint32_t w0, w1, w2, w3 = 0;
-        gen.words4(a, w0, w1, w2, w3);
-        atomicAdd(&bk[other_word<FULL>(o, a, w0, w3)], order_qty(o, w2));
+    // the rest: a NOISE row cut by the class boundary, then MOMENTUM and MAKER agents
+    for (; b < d.A; b += nthr) {
+        const uint32_t a = b + t;
+        if (a < d.A) {
+            uint32_t w0, w1, w2, w3 = 0;
+            row_words<POW2>(gen, b, t, w0, w1, w2, w3);
+            const uint32_t w = a >= nn ? other_word<FULL>(o, a, w0, w3)
+                               : (FULL && o.mid) ? mid_noise_word(o, w0, w1, w3)
+                                                 : noise_word(o, w0, w1);
+            atomicAdd(&bk[w], order_qty(o, w2));
+        }
     }
 }
 
-template <bool FULL>
+template <bool FULL, bool POW2 = true>
 __device__ __forceinline__ void gen_orders(const DevMarket &d, uint32_t m, uint32_t s, const Refs &r,
                                            uint32_t key0, uint32_t key1, uint32_t t, uint32_t nthr,
                                            uint32_t *bk)
 {
     const OrderCtx o = order_ctx<FULL>(d, s, r);
     if (FULL && uses_splitmix(d)) {
-        gen_with<FULL>(d, o, SplitMixStep(s, m, d.A, ((uint64_t)key1 << 32) | key0), t, nthr, bk);
+        gen_with<FULL, POW2>(d, o, SplitMixStep(s, m, d.A, ((uint64_t)key1 << 32) | key0), t, nthr, bk);
         return;
     }
-    gen_with<FULL>(d, o, PhiloxStep(s, m, key0, key1), t, nthr, bk);
+    gen_with<FULL, POW2>(d, o, PhiloxStep(s, m, key0, key1), t, nthr, bk);
+}
+
+// Last-tick orders of step s aggregated by their position relative to the reference, before the
+// reference is known (section III-C: no rule of the last-tick model looks at the price until the
+// tick is formed).  Bins, as (bid, ask) pairs: pair o < 2K+1 holds the NOISE orders of offset
+// o - K; pair 2K+1 the MOMENTUM quantities by their coin (the trend decides at the flush whether
+// the coin or the trend picks the side); pair 2K+2 the MAKER quantities by side.  Agents
+// a0, a0 + stride, ... below `end`.
+template <typename Gen>
+__device__ __forceinline__ void gen_rel(const DevMarket &d, uint32_t s, const Gen &gen, uint32_t b0,
+                                        uint32_t stride, uint32_t end, uint32_t lane, uint32_t *H)
+{
+    // rows of 64 agents b | lane at the uniform bases b0, b0 + stride, ... (multiples of 64)
+    const uint32_t span = 2u * d.K + 1u;
+    const uint32_t nend = min(d.n_noise, end);
+    uint32_t b = b0;
+    // two full NOISE rows per pass: two independent generator chains for the wave to issue from
+    for (; b + stride + 64u <= nend; b += 2u * stride) {
+        uint32_t w0, w1, w2, w3, x0, x1, x2, x3;
+        gen.words4_row(b, lane, w0, w1, w2, w3);
+        gen.words4_row(b + stride, lane, x0, x1, x2, x3);
+        atomicAdd(&H[2u * __umulhi(w1, span) + (w0 >> 31)], 1u + __umulhi(w2, d.Q));
+        atomicAdd(&H[2u * __umulhi(x1, span) + (x0 >> 31)], 1u + __umulhi(x2, d.Q));
+    }
+    const uint32_t mom_end = d.n_noise + d.n_mom;
+    for (; b < end; b += stride) {
+        const uint32_t a = b | lane;
+        if (a < end) {
+            uint32_t w0, w1, w2, w3;
+            gen.words4_row(b, lane, w0, w1, w2, w3);
+            const uint32_t bin = a < nend ? 2u * __umulhi(w1, span) + (w0 >> 31)
+                                          : 2u * span + (a < mom_end ? (w0 >> 31) : 2u + ((a ^ s) & 1u));
+            atomicAdd(&H[bin], 1u + __umulhi(w2, d.Q));
+        }
+    }
+}
+
+// Adds the bins of one step to the book at reference `last` (momentum direction from last vs
+// prev, as order_ctx) and clears them; one 64-bit LDS add per target tick (a tick's bid count
+// cannot carry into its ask count: the host guard keeps every count below 2^32).  One wave.
+__device__ __forceinline__ void flush_rel(const DevMarket &d, uint32_t last, uint32_t prev, uint32_t *H,
+                                          uint32_t *bk, uint32_t lane)
+{
+    const uint32_t span = 2u * d.K + 1u;
+    const int l = (int)last, top = (int)d.L - 1, h = (int)d.h;
+    const uint32_t dir = last > prev ? 0u : (last < prev ? 1u : 2u);
+    uint2 *P = reinterpret_cast<uint2 *>(H);
+    for (uint32_t j = lane; j < span + 4u; j += 64u) {
+        const uint32_t pj = j < span ? j : (j < span + 2u ? span : span + 1u);
+        const uint2 v = P[pj];
+        uint64_t add;
+        int tick;
+        if (j < span) {
+            tick = l - (int)d.K + (int)j;
+            add = ((uint64_t)v.y << 32) | v.x;
+        } else if (j == span) {  // momentum buys at last + 1
+            tick = l + 1;
+            add = dir == 0u ? (uint64_t)(v.x + v.y) : (dir == 2u ? (uint64_t)v.x : 0u);
+        } else if (j == span + 1u) {  // momentum sells at last - 1
+            tick = l - 1;
+            add = (dir == 1u ? (uint64_t)(v.x + v.y) : (dir == 2u ? (uint64_t)v.y : 0u)) << 32;
+        } else if (j == span + 2u) {  // maker bids at last - h
+            tick = l - h;
+            add = v.x;
+        } else {  // maker asks at last + h
+            tick = l + h;
+            add = (uint64_t)v.y << 32;
+        }
+        tick = min(max(tick, 0), top);
+        if (add != 0) atomicAdd(reinterpret_cast<unsigned long long *>(bk) + tick, (unsigned long long)add);
+    }
+    wave_sync();
+    for (uint32_t j = lane; j < span + 2u; j += 64u) P[j] = make_uint2(0u, 0u);
 }
 
 // Best bid / best ask (kNone when a side is empty) of an LDS book, by one wave: the reference
@@ -815,6 +936,133 @@ __device__ __forceinline__ void run_market(const EngineArgs &args, const Item &i
     }
 }
 
+// Lock-step market of the last-tick model with the next step's orders generated while the
+// current step clears: in step i the clearing wave c = i mod wpm adds the bins of step i to the
+// book (reference = the price after step i - 1), clears it and then generates `share` rows of 64
+// agents of step i + 1; the other waves generate the rest of step i + 1 into the other bin
+// buffer, and the wave that cleared step i - 1 first adds that step's statistics.  One barrier
+// per step; no wave waits for a clearing.  Step 0 of the call is generated into the book
+// directly.  Same books, prices and statistics as run_market.
+template <int TPL_MAX, bool TRACE>
+__device__ __forceinline__ void run_market_ovl(const EngineArgs &args, const Item &item, uint32_t sub,
+                                               uint32_t w_in, uint32_t lane, bool active, uint32_t *lds)
+{
+    const uint32_t wpm_mask = (1u << item.wpm_log2) - 1u;
+    const uint32_t nthr = 64u << item.wpm_log2;
+    const uint32_t t = (w_in << 6) | lane;
+    uint32_t *bk = lds + sub * item.stride;
+    uint32_t *scr = bk + item.stride - kScr;
+    uint32_t *H0 = bk + item.hoff;
+    uint32_t *H1 = H0 + item.hwords;
+
+    uint32_t m = 0;
+    DevMarket d{};
+    uint32_t last = 0, prev = 0, ref2 = 0;
+    uint64_t steps0 = 0;
+    if (active) {
+        m = args.order[item.first + sub];
+        d = args.desc[m];
+        const cae_state *st = args.state + m;
+        last = st->last;
+        prev = st->prev;
+        steps0 = st->steps_done;
+        ref2 = st->ref2;
+        if (t < 14u) scr[8u + t] = reinterpret_cast<const uint32_t *>(st)[4u + t];  // n_trade .. sum_r2
+        const uint32_t *gb = args.book + d.book_off;
+        const uint32_t padded = 64u * d.tpl;
+        for (uint32_t q = t; q < padded; q += nthr) {
+            uint2 v = make_uint2(0u, 0u);
+            if (q < d.L) {
+                v.x = gb[q];
+                v.y = gb[d.L + q];
+            }
+            reinterpret_cast<uint2 *>(bk)[q] = v;
+        }
+        for (uint32_t q = t; q < 2u * item.hwords; q += nthr) H0[q] = 0u;
+    }
+    __syncthreads();
+    if (active) gen_orders<false>(d, d.id, (uint32_t)steps0, Refs{last, prev, 2u * last, 0u}, args.k0, args.k1, t,
+                                  nthr, bk);
+    __syncthreads();
+
+    const double *lnT = args.lnT + d.L;
+    const uint32_t own = min(d.A, item.share * 64u);        // agents of the clearing wave
+    const uint32_t ostride = nthr - 64u;                   // the other waves' stride
+    for (uint32_t i = 0; i < args.S; ++i) {
+        const uint32_t s = (uint32_t)steps0 + i;
+        const uint32_t c = i & wpm_mask;
+        uint32_t *Hn = (i & 1u) ? H0 : H1;  // bins of step i + 1
+        const bool more = i + 1u < args.S;
+        if (active && w_in == c) {
+            __builtin_amdgcn_s_setprio(3);
+            if (i >= 1u) flush_rel(d, last, prev, (i & 1u) ? H1 : H0, bk, lane);
+            wave_sync();
+            const ClearOut co = clear_dispatch<TPL_MAX>(bk, d.tpl, lane);
+            if (lane == 0) *reinterpret_cast<uint4 *>(scr + 4u * (i & 1u)) = make_uint4(co.p, co.v, co.bb, co.ba);
+            if (more) gen_rel(d, s + 1u, PhiloxStep(s + 1u, d.id, args.k0, args.k1), 0u, 64u, own, lane, Hn);
+            __builtin_amdgcn_s_setprio(0);
+        } else if (active) {
+            if (i >= 1u && w_in == ((c - 1u) & wpm_mask))
+                stats_to_lds(scr, scr + 4u * ((i - 1u) & 1u), last, prev, lnT, lane);  // step i - 1
+            if (more) {
+                const uint32_t r = (w_in - c - 1u) & wpm_mask;  // 0 .. wpm - 2
+                gen_rel(d, s + 1u, PhiloxStep(s + 1u, d.id, args.k0, args.k1), own + (r << 6), ostride, d.A,
+                        lane, Hn);
+            }
+        }
+        __syncthreads();
+        if (active) {
+            const uint4 r = *reinterpret_cast<const uint4 *>(scr + 4u * (i & 1u));
+            const uint32_t p = (uint32_t)__builtin_amdgcn_readfirstlane((int)r.x);
+            const uint32_t v = (uint32_t)__builtin_amdgcn_readfirstlane((int)r.y);
+            ref2 = 2u * last;
+            prev = last;
+            if (v != 0) last = p;
+            if constexpr (TRACE) {
+                if (t == 0) trace_step(args, m, i, last, v);
+            }
+        }
+    }
+    uint64_t n_trade = 0, sum_vol = 0, sum_px = 0, sum_spread = 0, n_spread = 0;
+    double sum_r = 0.0, sum_r2 = 0.0;
+    if (active && w_in == 0u) {
+        // the last step's statistics; then wave 0 holds the totals of every step
+        if (args.S >= 1u) stats_to_lds(scr, scr + 4u * ((args.S - 1u) & 1u), last, prev, lnT, lane);
+        wave_sync();
+        const uint64_t *a = reinterpret_cast<const uint64_t *>(scr + 8);
+        const double *f = reinterpret_cast<const double *>(scr + 18);
+        n_trade = a[0];
+        sum_vol = a[1];
+        sum_px = a[2];
+        sum_spread = a[3];
+        n_spread = a[4];
+        sum_r = f[0];
+        sum_r2 = f[1];
+    }
+    if (active) {
+        uint32_t *gb = args.book + d.book_off;
+        for (uint32_t q = t; q < d.L; q += nthr) {
+            const uint2 v = reinterpret_cast<const uint2 *>(bk)[q];
+            gb[q] = v.x;
+            gb[d.L + q] = v.y;
+        }
+        if (t == 0) {
+            cae_state *st = args.state + m;
+            st->last = last;
+            st->prev = prev;
+            st->steps_done = steps0 + args.S;
+            st->n_trade = n_trade;
+            st->sum_vol = sum_vol;
+            st->sum_px = sum_px;
+            st->sum_spread = sum_spread;
+            st->n_spread = n_spread;
+            st->sum_r = sum_r;
+            st->sum_r2 = sum_r2;
+            st->ref2 = ref2;
+        }
+    }
+}
+
 // Scratch layout of a pipelined market (32-bit words): 0 last, 1 prev, 2-3 steps at item start,
 // 4-5 n_trade, 6-7 sum_vol, 8-9 sum_px, 10-11 sum_spread, 12-13 n_spread, 14-15 sum_r,
 // 16-17 sum_r2, 18 ref2 (2 x the previous step's reference), 19 reserved (words 0-19 are the
@@ -967,7 +1215,7 @@ __device__ __forceinline__ void run_pair(const EngineArgs &args, const Item &ite
                 r.mid2p = (uint32_t)__builtin_amdgcn_readfirstlane((int)scr[18]);
                 r.mid2 = (uint32_t)__builtin_amdgcn_readfirstlane((int)scr[20]);
             }
-            gen_orders<FULL>(dx, dx.id, s, r, args.k0, args.k1, (gidx << 6) | lane, (G - 1u) << 6, bk);
+            gen_orders<FULL, false>(dx, dx.id, s, r, args.k0, args.k1, (gidx << 6) | lane, (G - 1u) << 6, bk);
         }
         __syncthreads();
         gidx = gidx == 0u ? G - 1u : gidx - 1u;
@@ -1014,10 +1262,12 @@ __global__ void __launch_bounds__(1024) cae_engine_kernel(const EngineArgs args)
         const uint32_t sub = wave >> item.wpm_log2;
         const uint32_t w_in = wave & ((1u << item.wpm_log2) - 1u);
         const bool active = sub < item.count;
-        if (item.pipe) {
+        if (item.pipe == 1u) {
             run_pair<TPL_MAX, FULL, TRACE>(args, item, wave, lane, blockDim.x >> 6, lds);
         } else if (item.wpm_log2 == 0) {
             if (active) run_market<TPL_MAX, false, FULL, TRACE>(args, item, sub, w_in, lane, true, lds);
+        } else if (!FULL && item.pipe == 2u) {
+            run_market_ovl<TPL_MAX, TRACE>(args, item, sub, w_in, lane, active, lds);
         } else {
             run_market<TPL_MAX, true, FULL, TRACE>(args, item, sub, w_in, lane, active, lds);
         }
@@ -1208,6 +1458,16 @@ uint32_t tpl_for(uint32_t L)
     return t;
 }
 
+// Words of one order-bin buffer of an overlapped market: 2K + 3 (bid, ask) pairs, rounded up to
+// a power of two of at least 64 so that markets of nearby K share items.
+constexpr uint32_t kMaxOverlapK = 1022;
+uint32_t hwords_for(uint32_t K)
+{
+    uint32_t w = 64;
+    while (w < 4u * K + 6u) w <<= 1;
+    return w;
+}
+
 uint32_t lclass(uint32_t L)
 {
     uint32_t c = 0;
@@ -1342,6 +1602,10 @@ int build_schedule(cae_ensemble *e, const cae_tuning *tn, const uint32_t *ids,
     if (tn) t = *tn;
     std::vector<uint32_t> wpm(M);
     uint32_t wpm_max = 1, tpl_max = 1;
+    for (uint32_t m = 0; m < M; ++m)
+        e->any_mid |= (e->desc[m].flags & CAE_MODEL_MASK) == CAE_MODEL_MID ||
+                      ((e->desc[m].flags >> CAE_GEN_SHIFT) & 0xFFu) == CAE_GEN_SPLITMIX;
+    if (e->any_mid) std::memset(t.overlap, 0, sizeof(t.overlap));
     for (uint32_t m = 0; m < M; ++m) {
         const cae_market &d = e->desc[m];
         const uint32_t c = lclass(d.L) * 8u + aclass(d.A);
@@ -1352,10 +1616,9 @@ int build_schedule(cae_ensemble *e, const cae_tuning *tn, const uint32_t *ids,
         if (t.pipelined[c]) w = 1;  // a pipelined pair uses the whole workgroup
         wpm[m] = w;
         t.waves_per_market[c] = (uint8_t)w;
+        if (w < 2 || e->any_mid) t.overlap[c] = 0;
         wpm_max = std::max(wpm_max, w);
         tpl_max = std::max(tpl_max, tpl_for(d.L));
-        e->any_mid |= (d.flags & CAE_MODEL_MASK) == CAE_MODEL_MID ||
-                      ((d.flags >> CAE_GEN_SHIFT) & 0xFFu) == CAE_GEN_SPLITMIX;
     }
     uint32_t G = t.waves_per_group;
     if (G == 0) G = std::max(wpm_max, 4u);
@@ -1382,22 +1645,27 @@ int build_schedule(cae_ensemble *e, const cae_tuning *tn, const uint32_t *ids,
     if (!keep)
         std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return cost[a] > cost[b]; });
 
-    // open bins per (wpm, tpl, pipelined)
-    struct Bin { std::vector<uint32_t> ms; uint32_t wpm, tpl, pipe; };
+    // open bins per (wpm, tpl, mode, clearing share, bin buffer size)
+    struct Bin { std::vector<uint32_t> ms; uint32_t wpm, tpl, pipe, share, hw; };
     std::vector<Bin> open;
     std::vector<std::pair<double, Bin>> done;
     for (uint32_t idx = 0; idx < M; ++idx) {
         const uint32_t m = order[idx];
         const uint32_t w = wpm[m], tp = tpl_for(e->desc[m].L);
-        const uint32_t pp = t.pipelined[lclass(e->desc[m].L) * 8u + aclass(e->desc[m].A)] ? 1u : 0u;
-        const uint32_t stride = 2u * 64u * tp + kScr;
-        uint32_t cap = pp ? 2u : G / w;
+        const uint32_t c = lclass(e->desc[m].L) * 8u + aclass(e->desc[m].A);
+        // overlapped markets keep 2 x (2K + 3) bin pairs in LDS; wider offset ranges run plain
+        const uint32_t ov = e->desc[m].K <= kMaxOverlapK ? t.overlap[c] : 0u;
+        const uint32_t pp = t.pipelined[c] ? 1u : (ov ? 2u : 0u);
+        const uint32_t share = ov ? ov - 1u : 0u;
+        const uint32_t hw = ov ? hwords_for(e->desc[m].K) : 0u;
+        const uint32_t stride = 2u * 64u * tp + 2u * hw + kScr;
+        uint32_t cap = pp == 1u ? 2u : G / w;
         cap = std::max(1u, std::min(cap, lds_budget / (stride * 4u)));
         Bin *b = nullptr;
         for (auto &x : open)
-            if (x.wpm == w && x.tpl == tp && x.pipe == pp) b = &x;
+            if (x.wpm == w && x.tpl == tp && x.pipe == pp && x.share == share && x.hw == hw) b = &x;
         if (!b) {
-            open.push_back(Bin{{}, w, tp, pp});
+            open.push_back(Bin{{}, w, tp, pp, share, hw});
             b = &open.back();
         }
         b->ms.push_back(m);
@@ -1426,8 +1694,11 @@ int build_schedule(cae_ensemble *e, const cae_tuning *tn, const uint32_t *ids,
         it.first = (uint32_t)order.size();
         it.count = (uint32_t)b.ms.size();
         it.wpm_log2 = (uint32_t)__builtin_ctz(b.wpm);
-        it.stride = 2u * 64u * b.tpl + kScr;
+        it.stride = 2u * 64u * b.tpl + 2u * b.hw + kScr;
         it.pipe = b.pipe;
+        it.share = b.share;
+        it.hoff = 2u * 64u * b.tpl;
+        it.hwords = b.hw;
         for (uint32_t mm : b.ms) order.push_back(mm);
         items.push_back(it);
         lds_max = std::max(lds_max, it.count * it.stride * 4u);

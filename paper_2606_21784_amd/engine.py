@@ -60,8 +60,8 @@ def sizes(descs):
 
 def tuning_struct(t=None):
     """A cae_tuning from a dict {waves_per_group, groups_per_cu, max_lds_bytes, flags,
-    waves_per_market: {class: waves}, pipelined: {class: 1}, class_cost_ns: {class: ns}}
-    (or None)."""
+    waves_per_market: {class: waves}, pipelined: {class: 1}, overlap: {class: k},
+    class_cost_ns: {class: ns}} (or None)."""
     if t is None:
         return None
     if isinstance(t, Tuning):
@@ -75,6 +75,8 @@ def tuning_struct(t=None):
         ts.waves_per_market[int(c)] = int(w)
     for c, v in dict(t.get("pipelined", {})).items():
         ts.pipelined[int(c)] = 1 if v else 0
+    for c, v in dict(t.get("overlap", {})).items():
+        ts.overlap[int(c)] = int(v)
     for c, v in dict(t.get("class_cost_ns", {})).items():
         ts.class_cost[int(c)] = float(v)
     return ts
@@ -203,6 +205,7 @@ class Ensemble:
                 "waves_per_market": {c: int(t.waves_per_market[c])
                                      for c in range(_lib.NUM_CLASSES) if t.waves_per_market[c]},
                 "pipelined": {c: 1 for c in range(_lib.NUM_CLASSES) if t.pipelined[c]},
+                "overlap": {c: int(t.overlap[c]) for c in range(_lib.NUM_CLASSES) if t.overlap[c]},
                 "class_cost_ns": {c: float(t.class_cost[c])
                                   for c in range(_lib.NUM_CLASSES) if t.class_cost[c] > 0}}
 

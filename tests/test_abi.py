@@ -37,7 +37,24 @@ def test_struct_layouts(cae):
     assert C.sizeof(cae.Market) == 32
     assert C.sizeof(cae.State) == 80
     assert C.sizeof(cae.Sizes) == 32
-    assert C.sizeof(cae.Tuning) == 16 + 6 * cae.NUM_CLASSES
+    assert C.sizeof(cae.Tuning) == 16 + 7 * cae.NUM_CLASSES
+
+
+def test_header_struct_sizes_match_binding(cae, tmp_path):
+    """The header's structs, compiled by the host C compiler, have the binding's sizes."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    src = tmp_path / "sizes.c"
+    checks = [("cae_market", C.sizeof(cae.Market)), ("cae_state", C.sizeof(cae.State)),
+              ("cae_sizes_t", C.sizeof(cae.Sizes)), ("cae_tuning", C.sizeof(cae.Tuning))]
+    src.write_text('#include "cae.h"\n' + "".join(
+        "_Static_assert(sizeof(%s) == %d, \"%s\");\n" % (n, z, n) for n, z in checks))
+    r = subprocess.run([cc, "-std=c11", "-fsyntax-only", "-I", os.path.join(ROOT, "include"), str(src)],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
 
 
 def test_strerror(cae):

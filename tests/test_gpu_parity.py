@@ -334,6 +334,88 @@ def test_pipelined_mixed_with_other_modes():
     _assert_states(st, rst)
 
 
+@pytest.mark.parametrize("wpm,G,k", [(2, 2, 1), (2, 8, 2), (4, 4, 1), (4, 4, 2), (4, 8, 5),
+                                     (8, 8, 3), (16, 16, 1), (4, 4, 200)])
+def test_overlapped_lockstep_exact(wpm, G, k):
+    """Lock-step markets that generate the next step's orders during the clearing (clearing
+    wave taking k - 1 rows of agents, from none to all of them) give the oracle's books, over
+    calls of 33, 1 and 17 steps."""
+    descs = W.uniform(7, 100, 700, 9, 20, n_noise=350, n_mom=190, h=3)
+    tn = {"waves_per_group": G, "waves_per_market": {c: wpm for c in range(40)},
+          "overlap": {c: k for c in range(40)}}
+    st, bk, used = _run_gpu(descs, 21, [33, 1, 17], tuning=tn)
+    assert set(used["overlap"].values()) == {k}
+    rst, rbk = O.run(descs, 21, 51)
+    _assert_books(descs, bk, rbk)
+    _assert_states(st, rst)
+
+
+@pytest.mark.parametrize("cfg", [
+    # L, A, K, Q, n_noise, n_mom, h  -- clamped offsets, agents fewer than a wave, one class only
+    (1, 1, 0, 1, 1, 0, 0),
+    (3, 65, 2, 7, 65, 0, 1),
+    (100, 1000, 9, 33, 500, 300, 3),
+    (257, 777, 16, 100, 300, 300, 5),
+    (1000, 130, 40, 5, 0, 130, 7),
+    (1024, 3000, 64, 100, 1000, 1000, 2),
+    (64, 64, 8, 10, 0, 0, 2),
+    (64, 40, 100, 10, 40, 0, 1),
+    (512, 5000, 1022, 50, 5000, 0, 1),
+    (512, 900, 1023, 50, 300, 300, 1),
+])
+def test_overlapped_ragged_markets(cfg):
+    """Overlapped lock-step on ragged shapes, offsets wider than the book, momentum-only and
+    maker-only populations, and K past the bin limit (those markets run plain lock-step)."""
+    L, A, K, Q, nn, nm, h = cfg
+    descs = W.uniform(5, L, A, K, Q, n_noise=nn, n_mom=nm, h=h)
+    tn = {"waves_per_group": 8, "waves_per_market": {c: 4 for c in range(40)},
+          "overlap": {c: 2 for c in range(40)}}
+    st, bk, _ = _run_gpu(descs, 12345, [40, 3], tuning=tn)
+    rst, rbk = O.run(descs, 12345, 43)
+    _assert_books(descs, bk, rbk)
+    _assert_states(st, rst)
+
+
+def test_overlapped_mixed_with_other_modes():
+    """Overlapped, plain lock-step, single-wave and pipelined classes in one launch."""
+    rng = np.random.default_rng(19)
+    n = 60
+    L = rng.choice([5, 64, 128, 256, 512, 1000], n)
+    A = rng.integers(1, 5000, n)
+    d = np.zeros(n, W.MARKET_DTYPE)
+    d["L"], d["A"], d["K"], d["Q"] = L, A, np.maximum(1, L // 16), rng.integers(1, 60, n)
+    d["n_noise"] = A // 2
+    d["n_mom"] = A // 3
+    d["h"] = np.minimum(2, L - 1)
+    from paper_2606_21784_amd import engine
+    cls = sorted(set(engine.size_class(int(a), int(b)) for a, b in zip(L, A)))
+    tn = {"waves_per_group": 8,
+          "waves_per_market": {c: (1 if c % 4 == 0 else 4) for c in cls},
+          "pipelined": {c: 1 for c in cls if c % 4 == 1},
+          "overlap": {c: 1 + c % 3 for c in cls if c % 4 in (0, 2, 3)}}
+    st, bk, used = _run_gpu(d, 77, [25, 6], tuning=tn)
+    # reported only where it applies: lock-step classes that are not pipelined
+    assert sorted(used["overlap"]) == [c for c in cls if c % 4 in (2, 3)]
+    rst, rbk = O.run(d, 77, 31)
+    _assert_books(d, bk, rbk)
+    _assert_states(st, rst)
+
+
+def test_overlap_is_ignored_for_mid_price_ensembles():
+    """The overlap applies to last-tick ensembles only; a mid-price market in the ensemble turns
+    it off (reported as 0) and the results stay exact."""
+    d = np.concatenate([W.uniform(3, 128, 600, 8, 10, n_noise=300, n_mom=200, h=2),
+                        W.uniform(3, 128, 600, 8, 10, n_noise=300, n_mom=200, h=2,
+                                  flags=O.model_flags(O.MODEL_MID, 3000))])
+    tn = {"waves_per_group": 4, "waves_per_market": {c: 4 for c in range(40)},
+          "overlap": {c: 2 for c in range(40)}}
+    st, bk, used = _run_gpu(d, 5, [20], tuning=tn)
+    assert used["overlap"] == {}
+    rst, rbk = O.run(d, 5, 20)
+    _assert_books(d, bk, rbk)
+    _assert_states(st, rst)
+
+
 @pytest.mark.parametrize("cfg", [(64, 128, 8, 10, 128, 0, 2), (100, 300, 9, 20, 150, 90, 3),
                                  (1024, 700, 40, 50, 200, 300, 2), (1, 5, 0, 3, 2, 2, 0)])
 def test_naive_engine_is_bit_identical(cfg):
@@ -356,7 +438,7 @@ def _u32(t):
     return t.cpu().numpy().view(np.uint32)
 
 
-@pytest.mark.parametrize("mode", ["lockstep", "single", "pipelined"])
+@pytest.mark.parametrize("mode", ["lockstep", "single", "pipelined", "overlapped"])
 def test_traced_series_match_oracle(mode):
     """cae_step_traced writes each market's per-step price and volume series equal to the
     oracle's, in every schedule mode; untraced calls leave their columns alone and tracing does
@@ -366,7 +448,9 @@ def test_traced_series_match_oracle(mode):
     descs = W.uniform(9, 100, 300, 9, 20, n_noise=150, n_mom=90, h=3)
     tn = {"lockstep": {"waves_per_group": 4, "waves_per_market": {c: 2 for c in range(40)}},
           "single": {"waves_per_group": 4, "waves_per_market": {c: 1 for c in range(40)}},
-          "pipelined": {"waves_per_group": 4, "pipelined": {c: 1 for c in range(40)}}}[mode]
+          "pipelined": {"waves_per_group": 4, "pipelined": {c: 1 for c in range(40)}},
+          "overlapped": {"waves_per_group": 4, "waves_per_market": {c: 4 for c in range(40)},
+                         "overlap": {c: 2 for c in range(40)}}}[mode]
     ens = E.Ensemble(descs, 21, tuning=tn)
     pr = torch.full((9, 80), -1, dtype=torch.int32, device="cuda")
     vo = torch.full((9, 80), -1, dtype=torch.int32, device="cuda")
@@ -408,7 +492,8 @@ def test_traced_mixed_sizes_and_modes():
     cls = [E.size_class(int(a), int(b)) for a, b in zip(L, A)]
     tn = {"waves_per_group": 8,
           "waves_per_market": {c: (1 if c % 3 == 0 else 4) for c in set(cls)},
-          "pipelined": {c: 1 for c in set(cls) if c % 3 == 1}}
+          "pipelined": {c: 1 for c in set(cls) if c % 3 == 1},
+          "overlap": {c: 2 for c in set(cls) if c % 6 == 2}}
     ens = E.Ensemble(d, 78, tuning=tn)
     pr, vo = ens.step_traced(40)
     torch.cuda.synchronize()
@@ -450,7 +535,9 @@ def test_mid_model_matches_oracle(mode, p_mkt):
     descs = W.uniform(9, 100, 300, 9, 20, n_noise=150, n_mom=90, h=3, flags=_mid(p_mkt))
     tn = {"lockstep": {"waves_per_group": 4, "waves_per_market": {c: 2 for c in range(40)}},
           "single": {"waves_per_group": 4, "waves_per_market": {c: 1 for c in range(40)}},
-          "pipelined": {"waves_per_group": 4, "pipelined": {c: 1 for c in range(40)}}}[mode]
+          "pipelined": {"waves_per_group": 4, "pipelined": {c: 1 for c in range(40)}},
+          "overlapped": {"waves_per_group": 4, "waves_per_market": {c: 4 for c in range(40)},
+                         "overlap": {c: 2 for c in range(40)}}}[mode]
     ens = E.Ensemble(descs, 31, tuning=tn)
     ens.step(13)
     pr, vo = ens.step_traced(40)
@@ -537,7 +624,9 @@ def test_splitmix_generator_matches_oracle(mode, model):
     descs["flags"][::3] = 0  # some Philox markets in the same launch
     tn = {"lockstep": {"waves_per_group": 4, "waves_per_market": {c: 2 for c in range(40)}},
           "single": {"waves_per_group": 4, "waves_per_market": {c: 1 for c in range(40)}},
-          "pipelined": {"waves_per_group": 4, "pipelined": {c: 1 for c in range(40)}}}[mode]
+          "pipelined": {"waves_per_group": 4, "pipelined": {c: 1 for c in range(40)}},
+          "overlapped": {"waves_per_group": 4, "waves_per_market": {c: 4 for c in range(40)},
+                         "overlap": {c: 2 for c in range(40)}}}[mode]
     ens = E.Ensemble(descs, 0xDEADBEEF12345, tuning=tn, market_ids=np.arange(10) * 7 + 3)
     ens.step(11)
     pr, vo = ens.step_traced(20)
