@@ -135,10 +135,12 @@ def uneven_leg(reps=2):
     for c, idx in groups.items():
         wpm = tn["waves_per_market"][c]
         pipe = tn.get("pipelined", {}).get(c, 0)
+        ovl = tn.get("overlap", {}).get(c, 0)
         parts.append(engine.Ensemble(d[idx], w["seed"], market_ids=idx,
                                      tuning={"waves_per_group": max(4 if not pipe else 8, wpm),
                                              "waves_per_market": {c: wpm},
-                                             "pipelined": {c: pipe} if pipe else {}}))
+                                             "pipelined": {c: pipe} if pipe else {},
+                                             "overlap": {c: ovl} if ovl else {}}))
     t_split = timed(parts, reps)
     for e in parts:
         e.close()
@@ -149,7 +151,8 @@ def uneven_leg(reps=2):
            "per_size_events_per_s": events / t_split, "speedup_vs_per_size": t_split / t_batched,
            "schedule": {"waves_per_group": sched["waves_per_group"],
                         "groups_per_cu": sched["groups_per_cu"],
-                        "waves_per_market": {str(k): v for k, v in sched["waves_per_market"].items()}},
+                        "waves_per_market": {str(k): v for k, v in sched["waves_per_market"].items()},
+                        "overlap": {str(k): v for k, v in sched["overlap"].items()}},
            "tune_s": tune_s}
     log("uneven: batched %.1f ms (untuned %.1f), per-size %d launches %.1f ms" %
         (out["batched_ms"], out["untuned_batched_ms"], len(groups), out["per_size_ms"]))
@@ -218,7 +221,8 @@ def tuned_time(w, reps=2):
     ms = min(times)
     sched = {"waves_per_group": used["waves_per_group"],
              "waves_per_market": sorted(set(used["waves_per_market"].values())),
-             "pipelined": bool(used["pipelined"])}
+             "pipelined": bool(used["pipelined"]),
+             "overlap": sorted(set(used["overlap"].values()))}
     return ms, events / (ms * 1e-3), sched, times
 
 
@@ -331,7 +335,8 @@ def main():
     sched = ens.tuning()
     sched = {"waves_per_group": sched["waves_per_group"], "groups_per_cu": sched["groups_per_cu"],
              "waves_per_market": sorted(set(sched["waves_per_market"].values())),
-             "pipelined": bool(sched["pipelined"]), "autotune_s": tune_s}
+             "pipelined": bool(sched["pipelined"]), "overlap": sorted(set(sched["overlap"].values())),
+             "autotune_s": tune_s}
     log("schedule:", json.dumps(sched))
 
     for _ in range(args.warmup):

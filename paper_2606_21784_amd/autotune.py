@@ -5,6 +5,9 @@ The engine's schedule has these knobs (``cae_tuning`` in include/cae.h):
     one market's orders; the rest of the workgroup's waves belong to other markets;
   * pipelined, per size class: markets run in pairs that share all of a workgroup's waves in
     alternating phases (one wave clears one market while the others generate the other's);
+  * overlap, per size class (lock-step, last-tick ensembles): the market's other waves generate
+    the next step's orders while one wave clears, the clearing wave taking overlap - 1 rows of
+    64 agents after its clearing;
   * waves per workgroup: how many markets of one class share a workgroup (in lock-step when a
     market spans more than one wave) and therefore how the workgroup's LDS is partitioned into
     market slices;
@@ -96,6 +99,7 @@ def tune(descs, seed=0, S_probe=None, min_markets=None, cache=None, arch="gfx950
     cls = classes_of(descs)
     wpm = {}
     pipe_c = {}
+    ovl_c = {}
     cost = {}
     t0 = time.perf_counter()
     for c in sorted(set(cls.tolist())):
@@ -103,6 +107,7 @@ def tune(descs, seed=0, S_probe=None, min_markets=None, cache=None, arch="gfx950
         if key in cached:
             wpm[c] = int(cached[key]["waves_per_market"])
             pipe_c[c] = bool(cached[key].get("pipelined", False))
+            ovl_c[c] = int(cached[key].get("overlap", 0))
             cost[c] = float(cached[key]["ns_per_market_step"])
             continue
         idx = np.nonzero(cls == c)[0]
@@ -112,35 +117,52 @@ def tune(descs, seed=0, S_probe=None, min_markets=None, cache=None, arch="gfx950
         probe = _probe_set(descs, idx, n, rng)
         Sp = S_probe or probe_steps(probe)
         events = float(probe["A"].astype(np.float64).sum()) * Sp
-        cands = [(w, False, max(4, w)) for w in WPM_CANDIDATES] + [(1, True, G) for G in PIPE_GROUPS]
+        cands = [(w, False, max(4, w), 0) for w in WPM_CANDIDATES] + [(1, True, G, 0) for G in PIPE_GROUPS]
         best = None
         timings = []
-        for w, pipe, G in cands:
+
+        def run(w, pipe, G, k):
             tn = {"waves_per_group": G, "waves_per_market": {int(c): w}}
             if pipe:
                 tn["pipelined"] = {int(c): 1}
+            if k:
+                tn["overlap"] = {int(c): k}
             ms = _time_launch(probe, seed, tn, Sp)
             if log:
+                mode = ("pipelined G=%d" % G) if pipe else "wpm %2d" % w + (" overlap %d" % k if k else "")
                 log("class %2d (L<=%4d, A~2^%d) %s: %.3f ms, %.3g events/s" %
-                    (c, 64 << (c // 8), 6 + c % 8, ("pipelined G=%d" % G) if pipe else "wpm %2d" % w,
-                     ms, events / (ms * 1e-3)))
-            if best is None or ms < best[3]:
-                best = (w, pipe, G, ms)
-            timings.append((w, pipe, G, ms))
-        # fewest waves per market among the near-fastest (candidates are in increasing order)
-        best = next(x for x in timings if x[3] <= best[3] * (1.0 + TIE))
+                    (c, 64 << (c // 8), 6 + c % 8, mode, ms, events / (ms * 1e-3)))
+            timings.append((w, pipe, G, k, ms))
+            return ms
+
+        for w, pipe, G, k in cands:
+            run(w, pipe, G, k)
+        # overlapped lock-step around the fastest plain lock-step width: the clearing wave takes
+        # none, half or all of an even share of the market's rows of 64 agents
+        if overlap_possible(descs):
+            lock = min((x for x in timings if x[0] >= 2 and not x[1]), key=lambda x: x[4])
+            rows = -(-int(probe["A"].max()) // 64)
+            for w in sorted({lock[0], min(16, 2 * lock[0])}):
+                for share in sorted({0, rows // (2 * w), rows // w}):
+                    run(w, False, max(4, w), share + 1)
+        fastest = min(x[4] for x in timings)
+        # fewest waves per market among the near-fastest (plain candidates come first, in
+        # increasing order of waves per market)
+        best = next(x for x in timings if x[4] <= fastest * (1.0 + TIE))
         wpm[c] = best[0]
         pipe_c[c] = best[1]
+        ovl_c[c] = best[3]
         # per market-step cost when the class fills the GPU alone
-        cost[c] = best[3] * 1e6 / (len(probe) * Sp) * ncu
-        cached[key] = {"waves_per_market": wpm[c], "pipelined": bool(pipe_c[c]),
+        cost[c] = best[4] * 1e6 / (len(probe) * Sp) * ncu
+        cached[key] = {"waves_per_market": wpm[c], "pipelined": bool(pipe_c[c]), "overlap": ovl_c[c],
                        "ns_per_market_step": cost[c]}
     # waves per workgroup on the whole ensemble; classes that asked for more waves per market
     # than a candidate group holds are clamped to it
     best_g = None
     for G in GROUP_CANDIDATES:
         tn = {"waves_per_group": G, "waves_per_market": {int(c): min(w, G) for c, w in wpm.items()},
-              "pipelined": {int(c): 1 for c, p in pipe_c.items() if p}}
+              "pipelined": {int(c): 1 for c, p in pipe_c.items() if p},
+              "overlap": {int(c): k for c, k in ovl_c.items() if k}}
         ms = _time_launch(descs, seed, tn, S_probe or probe_steps(descs))
         if log:
             log("waves_per_group %2d: %.3f ms" % (G, ms))
@@ -159,9 +181,16 @@ def tune(descs, seed=0, S_probe=None, min_markets=None, cache=None, arch="gfx950
     result = {"waves_per_group": best_g[0],
               "waves_per_market": {int(c): int(w) for c, w in wpm.items()},
               "pipelined": {int(c): 1 for c, p in pipe_c.items() if p},
+              "overlap": {int(c): int(k) for c, k in ovl_c.items() if k},
               "class_cost_ns": {int(c): float(v) for c, v in cost.items()},
               "tune_seconds": time.perf_counter() - t0}
     return result
+
+
+def overlap_possible(descs):
+    """Whether the engine runs an overlapped schedule for these markets: last-tick agents and the
+    Philox generator in every market (flags 0)."""
+    return bool((descs["flags"] == 0).all())
 
 
 def per_size_groups(descs):
