@@ -115,7 +115,7 @@ __device__ __forceinline__ void mulhilo(uint32_t m, uint32_t x, uint32_t &hi, ui
 // Philox4x32-10 for counter (s, a, m, 0) and key (k0, k1), split into the part that is the same
 // for every agent of a market-step (rounds 1-3 without the agent word) and the per-agent rest.
 struct PhiloxStep {
-    uint32_t ua, ux3k, uz0, uz2, z3, k0, k1;
+    uint32_t ua, ux3k, uz0, uz2, z3k, k0, k1;
 
     __device__ __forceinline__ PhiloxStep(uint32_t s, uint32_t m, uint32_t key0, uint32_t key1)
     {
@@ -134,7 +134,7 @@ struct PhiloxStep {
         mulhilo(kM0, y0, h0, l0);
         uz0 = y1 ^ (key0 + 2u * kW0);  // z0 = hi(M1 y2) ^ uz0, z1 = lo(M1 y2)
         uz2 = h0 ^ (key1 + 2u * kW1);  // z2 = uz2 ^ y3
-        z3 = l0;
+        z3k = l0 ^ (key1 + 3u * kW1);  // z3 = lo(M0 y0) is agent-independent: round 4 adds it to its key
         k0 = key0;
         k1 = key1;
     }
@@ -166,9 +166,14 @@ struct PhiloxStep {
         mulhilo(kM0, x0, h, l);
         const uint32_t y2 = h ^ ux3k, y3 = l;
         mulhilo(kM1, y2, h, l);
-        uint32_t c0 = h ^ uz0, c1 = l, c2 = uz2 ^ y3, c3 = z3;
+        const uint32_t z0 = h ^ uz0, z1 = l, z2 = uz2 ^ y3;
+        // round 4 (key k + 3W)
+        uint32_t h0, l0, h1, l1;
+        mulhilo(kM0, z0, h0, l0);
+        mulhilo(kM1, z2, h1, l1);
+        uint32_t c0 = xor3(h1, z1, k0 + 3u * kW0), c1 = l1, c2 = h0 ^ z3k, c3 = l0;
 #pragma unroll
-        for (uint32_t r = 3; r < 10; ++r) {  // rounds 4..10 use key k + r W
+        for (uint32_t r = 4; r < 10; ++r) {  // rounds 5..10 use key k + r W
             uint32_t h0, l0, h1, l1;
             mulhilo(kM0, c0, h0, l0);
             mulhilo(kM1, c2, h1, l1);
@@ -556,13 +561,28 @@ __device__ __forceinline__ OrderCtx order_ctx(const DevMarket &d, uint32_t s, co
     return o;
 }
 
-__device__ __forceinline__ uint32_t order_qty(const OrderCtx &o, uint32_t w2) { return 1u + __umulhi(w2, o.Q); }
+// A tick clamped to [0, top] (top >= 0) in one v_med3_i32 (top may differ between lanes: the
+// naive engine runs one market per lane).
+__device__ __forceinline__ int clamp_tick(int x, int top)
+{
+    int r;
+    asm("v_med3_i32 %0, %1, 0, %2" : "=v"(r) : "v"(x), "v"(top));
+    return r;
+}
+
+// 1 + floor(w2 Q / 2^32): the high word of w2 Q + 2^32, one multiply-add
+__device__ __forceinline__ uint32_t qty1(uint32_t w2, uint32_t Q)
+{
+    return (uint32_t)(((uint64_t)w2 * Q + (1ull << 32)) >> 32);
+}
+
+__device__ __forceinline__ uint32_t order_qty(const OrderCtx &o, uint32_t w2) { return qty1(w2, o.Q); }
 
 // Last-tick NOISE agent: fair coin for the side (w0), uniform offset in {-K..K} (w1); book
 // word 2*tick+side.
 __device__ __forceinline__ uint32_t noise_word(const OrderCtx &o, uint32_t w0, uint32_t w1)
 {
-    const int tick = min(max(o.base + (int)__umulhi(w1, o.span), 0), o.top);
+    const int tick = clamp_tick(o.base + (int)__umulhi(w1, o.span), o.top);
     return 2u * (uint32_t)tick + (w0 >> 31);
 }
 
@@ -573,7 +593,7 @@ __device__ __forceinline__ uint32_t mid_noise_word(const OrderCtx &o, uint32_t w
     const uint32_t sell = w0 >> 31;
     int tick = (int)(uint32_t)((o.nbase + (uint64_t)o.twoK * (uint64_t)w1) >> 32);
     if (w3 < o.tmkt) tick = sell ? 0 : o.top;
-    tick = min(max(tick, 0), o.top);
+    tick = clamp_tick(tick, o.top);
     return 2u * (uint32_t)tick + sell;
 }
 
@@ -589,7 +609,7 @@ __device__ __forceinline__ uint32_t other_word(const OrderCtx &o, uint32_t a, ui
     const int span = mom ? o.mom_ask - o.mom_bid : o.mk_ask - o.mk_bid;
     int tick = lo + (int)sell * span;
     if (FULL && mom && w3 < o.tmkt) tick = sell ? 0 : o.top;
-    tick = min(max(tick, 0), o.top);
+    tick = clamp_tick(tick, o.top);
     return 2u * (uint32_t)tick + sell;
 }
 
@@ -672,8 +692,8 @@ __device__ __forceinline__ void gen_rel(const DevMarket &d, uint32_t s, const Ge
         uint32_t w0, w1, w2, w3, x0, x1, x2, x3;
         gen.words4_row(b, lane, w0, w1, w2, w3);
         gen.words4_row(b + stride, lane, x0, x1, x2, x3);
-        atomicAdd(&H[2u * __umulhi(w1, span) + (w0 >> 31)], 1u + __umulhi(w2, d.Q));
-        atomicAdd(&H[2u * __umulhi(x1, span) + (x0 >> 31)], 1u + __umulhi(x2, d.Q));
+        atomicAdd(&H[2u * __umulhi(w1, span) + (w0 >> 31)], qty1(w2, d.Q));
+        atomicAdd(&H[2u * __umulhi(x1, span) + (x0 >> 31)], qty1(x2, d.Q));
     }
     const uint32_t mom_end = d.n_noise + d.n_mom;
     for (; b < end; b += stride) {
@@ -683,47 +703,53 @@ __device__ __forceinline__ void gen_rel(const DevMarket &d, uint32_t s, const Ge
             gen.words4_row(b, lane, w0, w1, w2, w3);
             const uint32_t bin = a < nend ? 2u * __umulhi(w1, span) + (w0 >> 31)
                                           : 2u * span + (a < mom_end ? (w0 >> 31) : 2u + ((a ^ s) & 1u));
-            atomicAdd(&H[bin], 1u + __umulhi(w2, d.Q));
+            atomicAdd(&H[bin], qty1(w2, d.Q));
         }
     }
 }
 
 // Adds the bins of one step to the book at reference `last` (momentum direction from last vs
-// prev, as order_ctx) and clears them; one 64-bit LDS add per target tick (a tick's bid count
-// cannot carry into its ask count: the host guard keeps every count below 2^32).  One wave.
+// prev, as order_ctx) and clears them.  Lane j < 2K+1 adds noise pair j at tick last - K + j;
+// lanes 2K+1 .. 2K+4 add the momentum buys (last + 1), momentum sells (last - 1), maker bids
+// (last - h) and maker asks (last + h); every tick clamped to the book.  One 64-bit LDS add per
+// lane, without branches (a tick's bid count cannot carry into its ask count: the host guard
+// keeps every count below 2^32).  One wave.
 __device__ __forceinline__ void flush_rel(const DevMarket &d, uint32_t last, uint32_t prev, uint32_t *H,
                                           uint32_t *bk, uint32_t lane)
 {
     const uint32_t span = 2u * d.K + 1u;
     const int l = (int)last, top = (int)d.L - 1, h = (int)d.h;
-    const uint32_t dir = last > prev ? 0u : (last < prev ? 1u : 2u);
+    const bool up = last > prev, down = last < prev, flat = last == prev;
     uint2 *P = reinterpret_cast<uint2 *>(H);
-    for (uint32_t j = lane; j < span + 4u; j += 64u) {
-        const uint32_t pj = j < span ? j : (j < span + 2u ? span : span + 1u);
-        const uint2 v = P[pj];
-        uint64_t add;
+    for (uint32_t j0 = 0; j0 < span + 4u; j0 += 64u) {
+        const uint32_t j = j0 + lane;
+        const uint32_t e = j - span;  // 0..3 for the momentum and maker lanes
+        const bool noise = j < span;
+        const uint32_t pj = noise ? j : span + min(e >> 1, 1u);
+        const uint2 v = P[min(pj, span + 1u)];
+        // momentum: buys take everything when the trend is up, the coin's buys when it is flat
+        const uint32_t mom = v.x + v.y;
+        const uint32_t mbuy = up ? mom : (flat ? v.x : 0u);
+        const uint32_t msell = down ? mom : (flat ? v.y : 0u);
+        uint32_t lo, hi;
         int tick;
-        if (j < span) {
+        if (noise) {
+            lo = v.x;
+            hi = v.y;
             tick = l - (int)d.K + (int)j;
-            add = ((uint64_t)v.y << 32) | v.x;
-        } else if (j == span) {  // momentum buys at last + 1
-            tick = l + 1;
-            add = dir == 0u ? (uint64_t)(v.x + v.y) : (dir == 2u ? (uint64_t)v.x : 0u);
-        } else if (j == span + 1u) {  // momentum sells at last - 1
-            tick = l - 1;
-            add = (dir == 1u ? (uint64_t)(v.x + v.y) : (dir == 2u ? (uint64_t)v.y : 0u)) << 32;
-        } else if (j == span + 2u) {  // maker bids at last - h
-            tick = l - h;
-            add = v.x;
-        } else {  // maker asks at last + h
-            tick = l + h;
-            add = (uint64_t)v.y << 32;
+        } else {
+            lo = e == 0u ? mbuy : (e == 2u ? v.x : 0u);
+            hi = e == 1u ? msell : (e == 3u ? v.y : 0u);
+            const int dlt = (e & 2u) ? h : 1;
+            tick = (e == 1u || e == 2u) ? l - dlt : l + dlt;
         }
-        tick = min(max(tick, 0), top);
-        if (add != 0) atomicAdd(reinterpret_cast<unsigned long long *>(bk) + tick, (unsigned long long)add);
+        tick = clamp_tick(tick, top);
+        if (j < span + 4u)
+            atomicAdd(reinterpret_cast<unsigned long long *>(bk) + tick, ((unsigned long long)hi << 32) | lo);
     }
-    wave_sync();
-    for (uint32_t j = lane; j < span + 2u; j += 64u) P[j] = make_uint2(0u, 0u);
+    // after every pass has read its bins (one wave's LDS accesses execute in order)
+    for (uint32_t j0 = 0; j0 < span + 2u; j0 += 64u)
+        if (j0 + lane < span + 2u) P[j0 + lane] = make_uint2(0u, 0u);
 }
 
 // Best bid / best ask (kNone when a side is empty) of an LDS book, by one wave: the reference
