@@ -1012,6 +1012,8 @@ __device__ __forceinline__ void run_market_ovl(const EngineArgs &args, const Ite
     __syncthreads();
 
     const double *lnT = args.lnT + d.L;
+    double *f = reinterpret_cast<double *>(scr + 18);      // sum_r, sum_r2 (in step order)
+    uint64_t n_trade = 0, sum_vol = 0, sum_px = 0, sum_spread = 0, n_spread = 0;  // this wave's steps
     const uint32_t own = min(d.A, item.share * 64u);        // agents of the clearing wave
     const uint32_t ostride = nthr - 64u;                   // the other waves' stride
     for (uint32_t i = 0; i < args.S; ++i) {
@@ -1025,11 +1027,27 @@ __device__ __forceinline__ void run_market_ovl(const EngineArgs &args, const Ite
             wave_sync();
             const ClearOut co = clear_dispatch<TPL_MAX>(bk, d.tpl, lane);
             if (lane == 0) *reinterpret_cast<uint4 *>(scr + 4u * (i & 1u)) = make_uint4(co.p, co.v, co.bb, co.ba);
+            // this step's statistics: integer totals in this wave's registers (added to the
+            // others at the end), the floating-point sums in step order in LDS; the loads are
+            // issued before and the sums stored after the wave's share of the next orders
+            if (co.v != 0) {
+                n_trade += 1;
+                sum_vol += co.v;
+                sum_px += co.p;
+            }
+            if (co.bb != kNone && co.ba != kNone) {
+                sum_spread += (uint64_t)(co.ba - co.bb);
+                n_spread += 1;
+            }
+            const double x = lnT[co.v != 0 ? co.p : last] - lnT[last];
+            const double f0 = f[0], f1 = f[1];
             if (more) gen_rel(d, s + 1u, PhiloxStep(s + 1u, d.id, args.k0, args.k1), 0u, 64u, own, lane, Hn);
+            if (lane == 0) {
+                f[0] = f0 + x;
+                f[1] = f1 + x * x;
+            }
             __builtin_amdgcn_s_setprio(0);
         } else if (active) {
-            if (i >= 1u && w_in == ((c - 1u) & wpm_mask))
-                stats_to_lds(scr, scr + 4u * ((i - 1u) & 1u), last, prev, lnT, lane);  // step i - 1
             if (more) {
                 const uint32_t r = (w_in - c - 1u) & wpm_mask;  // 0 .. wpm - 2
                 gen_rel(d, s + 1u, PhiloxStep(s + 1u, d.id, args.k0, args.k1), own + (r << 6), ostride, d.A,
@@ -1049,14 +1067,19 @@ __device__ __forceinline__ void run_market_ovl(const EngineArgs &args, const Ite
             }
         }
     }
-    uint64_t n_trade = 0, sum_vol = 0, sum_px = 0, sum_spread = 0, n_spread = 0;
+    // every wave adds the integer totals of the steps it cleared; then wave 0 holds all totals
+    if (active && lane == 0) {
+        unsigned long long *a = reinterpret_cast<unsigned long long *>(scr + 8);
+        atomicAdd(a + 0, (unsigned long long)n_trade);
+        atomicAdd(a + 1, (unsigned long long)sum_vol);
+        atomicAdd(a + 2, (unsigned long long)sum_px);
+        atomicAdd(a + 3, (unsigned long long)sum_spread);
+        atomicAdd(a + 4, (unsigned long long)n_spread);
+    }
+    __syncthreads();
     double sum_r = 0.0, sum_r2 = 0.0;
     if (active && w_in == 0u) {
-        // the last step's statistics; then wave 0 holds the totals of every step
-        if (args.S >= 1u) stats_to_lds(scr, scr + 4u * ((args.S - 1u) & 1u), last, prev, lnT, lane);
-        wave_sync();
         const uint64_t *a = reinterpret_cast<const uint64_t *>(scr + 8);
-        const double *f = reinterpret_cast<const double *>(scr + 18);
         n_trade = a[0];
         sum_vol = a[1];
         sum_px = a[2];
