@@ -137,14 +137,17 @@ def tune(descs, seed=0, S_probe=None, min_markets=None, cache=None, arch="gfx950
 
         for w, pipe, G, k in cands:
             run(w, pipe, G, k)
-        # overlapped lock-step around the fastest plain lock-step width: the clearing wave takes
-        # none, half or all of an even share of the market's rows of 64 agents
+        # overlapped lock-step at the fastest plain lock-step width, one or two markets per
+        # workgroup: the clearing wave takes from none to all of an even share of the market's
+        # rows of 64 agents (at most 5 steps)
         if overlap_possible(descs):
             lock = min((x for x in timings if x[0] >= 2 and not x[1]), key=lambda x: x[4])
+            w = lock[0]
             rows = -(-int(probe["A"].max()) // 64)
-            for w in sorted({lock[0], min(16, 2 * lock[0])}):
-                for share in sorted({0, rows // (2 * w), rows // w}):
-                    run(w, False, max(4, w), share + 1)
+            even = rows // w
+            for G in sorted({max(4, w), min(16, 2 * max(4, w))}):
+                for share in sorted({min(even, (even * j + 3) // 4) for j in range(5)}):
+                    run(w, False, G, share + 1)
         fastest = min(x[4] for x in timings)
         # fewest waves per market among the near-fastest (plain candidates come first, in
         # increasing order of waves per market)
