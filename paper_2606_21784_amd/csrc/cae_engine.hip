@@ -963,12 +963,22 @@ __device__ __forceinline__ void run_market(const EngineArgs &args, const Item &i
 }
 
 // Lock-step market of the last-tick model with the next step's orders generated while the
-// current step clears: in step i the clearing wave c = i mod wpm adds the bins of step i to the
-// book (reference = the price after step i - 1), clears it and then generates `share` rows of 64
-// agents of step i + 1; the other waves generate the rest of step i + 1 into the other bin
-// buffer, and the wave that cleared step i - 1 first adds that step's statistics.  One barrier
-// per step; no wave waits for a clearing.  Step 0 of the call is generated into the book
-// directly.  Same books, prices and statistics as run_market.
+// current step clears.  One wave at a time owns the clearing for a block of kOvlBlock steps (the
+// role rotates over the market's waves block by block, which spreads the clearing over the
+// SIMDs): in step i the owner adds the bins of step i to the book at the reference of step
+// i - 1's price, clears it, keeps the step's price and statistics in its registers and then
+// generates `share` rows of 64 agents of step i + 1; the other waves generate the rest of step
+// i + 1 into the other bin buffer.  No other wave needs the price: one barrier per step, no LDS
+// round trip for the result, and no wave waits for a clearing.  At the end of its block the
+// owner hands the price and the floating-point sums (kept in step order) to the next owner
+// through LDS.  Step 0 of the call is generated into the book directly.  Same books, prices
+// and statistics as run_market.
+//
+// Scratch words: 0 last, 1 prev, 2 ref2 (hand-over), 4-5 sum_r, 6-7 sum_r2 (hand-over), 8-17
+// n_trade, sum_vol, sum_px, sum_spread, n_spread (each wave's totals added at the end).
+constexpr uint32_t kOvlBlockLog2 = 4;
+constexpr uint32_t kOvlBlock = 1u << kOvlBlockLog2;
+
 template <int TPL_MAX, bool TRACE>
 __device__ __forceinline__ void run_market_ovl(const EngineArgs &args, const Item &item, uint32_t sub,
                                                uint32_t w_in, uint32_t lane, bool active, uint32_t *lds)
@@ -980,11 +990,13 @@ __device__ __forceinline__ void run_market_ovl(const EngineArgs &args, const Ite
     uint32_t *scr = bk + item.stride - kScr;
     uint32_t *H0 = bk + item.hoff;
     uint32_t *H1 = H0 + item.hwords;
+    double *fs = reinterpret_cast<double *>(scr + 4);
 
     uint32_t m = 0;
     DevMarket d{};
     uint32_t last = 0, prev = 0, ref2 = 0;
     uint64_t steps0 = 0;
+    double sum_r = 0.0, sum_r2 = 0.0;
     if (active) {
         m = args.order[item.first + sub];
         d = args.desc[m];
@@ -993,7 +1005,9 @@ __device__ __forceinline__ void run_market_ovl(const EngineArgs &args, const Ite
         prev = st->prev;
         steps0 = st->steps_done;
         ref2 = st->ref2;
-        if (t < 14u) scr[8u + t] = reinterpret_cast<const uint32_t *>(st)[4u + t];  // n_trade .. sum_r2
+        sum_r = st->sum_r;
+        sum_r2 = st->sum_r2;
+        if (t < 10u) scr[8u + t] = reinterpret_cast<const uint32_t *>(st)[4u + t];  // n_trade .. n_spread
         const uint32_t *gb = args.book + d.book_off;
         const uint32_t padded = 64u * d.tpl;
         for (uint32_t q = t; q < padded; q += nthr) {
@@ -1012,24 +1026,27 @@ __device__ __forceinline__ void run_market_ovl(const EngineArgs &args, const Ite
     __syncthreads();
 
     const double *lnT = args.lnT + d.L;
-    double *f = reinterpret_cast<double *>(scr + 18);      // sum_r, sum_r2 (in step order)
     uint64_t n_trade = 0, sum_vol = 0, sum_px = 0, sum_spread = 0, n_spread = 0;  // this wave's steps
     const uint32_t own = min(d.A, item.share * 64u);        // agents of the clearing wave
     const uint32_t ostride = nthr - 64u;                   // the other waves' stride
     for (uint32_t i = 0; i < args.S; ++i) {
         const uint32_t s = (uint32_t)steps0 + i;
-        const uint32_t c = i & wpm_mask;
+        const uint32_t c = (i >> kOvlBlockLog2) & wpm_mask;
         uint32_t *Hn = (i & 1u) ? H0 : H1;  // bins of step i + 1
         const bool more = i + 1u < args.S;
         if (active && w_in == c) {
             __builtin_amdgcn_s_setprio(3);
+            if (i != 0u && (i & (kOvlBlock - 1u)) == 0u) {  // first step of this wave's block
+                const uint4 h = *reinterpret_cast<const uint4 *>(scr);
+                last = (uint32_t)__builtin_amdgcn_readfirstlane((int)h.x);
+                prev = (uint32_t)__builtin_amdgcn_readfirstlane((int)h.y);
+                ref2 = (uint32_t)__builtin_amdgcn_readfirstlane((int)h.z);
+                sum_r = fs[0];
+                sum_r2 = fs[1];
+            }
             if (i >= 1u) flush_rel(d, last, prev, (i & 1u) ? H1 : H0, bk, lane);
             wave_sync();
             const ClearOut co = clear_dispatch<TPL_MAX>(bk, d.tpl, lane);
-            if (lane == 0) *reinterpret_cast<uint4 *>(scr + 4u * (i & 1u)) = make_uint4(co.p, co.v, co.bb, co.ba);
-            // this step's statistics: integer totals in this wave's registers (added to the
-            // others at the end), the floating-point sums in step order in LDS; the loads are
-            // issued before and the sums stored after the wave's share of the next orders
             if (co.v != 0) {
                 n_trade += 1;
                 sum_vol += co.v;
@@ -1039,35 +1056,33 @@ __device__ __forceinline__ void run_market_ovl(const EngineArgs &args, const Ite
                 sum_spread += (uint64_t)(co.ba - co.bb);
                 n_spread += 1;
             }
-            const double x = lnT[co.v != 0 ? co.p : last] - lnT[last];
-            const double f0 = f[0], f1 = f[1];
-            if (more) gen_rel(d, s + 1u, PhiloxStep(s + 1u, d.id, args.k0, args.k1), 0u, 64u, own, lane, Hn);
-            if (lane == 0) {
-                f[0] = f0 + x;
-                f[1] = f1 + x * x;
-            }
-            __builtin_amdgcn_s_setprio(0);
-        } else if (active) {
-            if (more) {
-                const uint32_t r = (w_in - c - 1u) & wpm_mask;  // 0 .. wpm - 2
-                gen_rel(d, s + 1u, PhiloxStep(s + 1u, d.id, args.k0, args.k1), own + (r << 6), ostride, d.A,
-                        lane, Hn);
-            }
-        }
-        __syncthreads();
-        if (active) {
-            const uint4 r = *reinterpret_cast<const uint4 *>(scr + 4u * (i & 1u));
-            const uint32_t p = (uint32_t)__builtin_amdgcn_readfirstlane((int)r.x);
-            const uint32_t v = (uint32_t)__builtin_amdgcn_readfirstlane((int)r.y);
             ref2 = 2u * last;
             prev = last;
-            if (v != 0) last = p;
+            if (co.v != 0) last = co.p;
             if constexpr (TRACE) {
-                if (t == 0) trace_step(args, m, i, last, v);
+                if (lane == 0) trace_step(args, m, i, last, co.v);
             }
+            // the log-table loads are issued here and consumed after the wave's rows
+            const double x = lnT[last] - lnT[prev];
+            if (more) gen_rel(d, s + 1u, PhiloxStep(s + 1u, d.id, args.k0, args.k1), 0u, 64u, own, lane, Hn);
+            sum_r = sum_r + x;
+            sum_r2 = sum_r2 + x * x;
+            if (((i + 1u) & (kOvlBlock - 1u)) == 0u || !more) {  // hand over (or finish)
+                if (lane == 0) {
+                    *reinterpret_cast<uint4 *>(scr) = make_uint4(last, prev, ref2, 0u);
+                    fs[0] = sum_r;
+                    fs[1] = sum_r2;
+                }
+            }
+            __builtin_amdgcn_s_setprio(0);
+        } else if (active && more) {
+            const uint32_t r = (w_in - c - 1u) & wpm_mask;  // 0 .. wpm - 2
+            gen_rel(d, s + 1u, PhiloxStep(s + 1u, d.id, args.k0, args.k1), own + (r << 6), ostride, d.A, lane,
+                    Hn);
         }
+        __syncthreads();
     }
-    // every wave adds the integer totals of the steps it cleared; then wave 0 holds all totals
+    // every wave adds the integer totals of the steps it cleared
     if (active && lane == 0) {
         unsigned long long *a = reinterpret_cast<unsigned long long *>(scr + 8);
         atomicAdd(a + 0, (unsigned long long)n_trade);
@@ -1077,17 +1092,6 @@ __device__ __forceinline__ void run_market_ovl(const EngineArgs &args, const Ite
         atomicAdd(a + 4, (unsigned long long)n_spread);
     }
     __syncthreads();
-    double sum_r = 0.0, sum_r2 = 0.0;
-    if (active && w_in == 0u) {
-        const uint64_t *a = reinterpret_cast<const uint64_t *>(scr + 8);
-        n_trade = a[0];
-        sum_vol = a[1];
-        sum_px = a[2];
-        sum_spread = a[3];
-        n_spread = a[4];
-        sum_r = f[0];
-        sum_r2 = f[1];
-    }
     if (active) {
         uint32_t *gb = args.book + d.book_off;
         for (uint32_t q = t; q < d.L; q += nthr) {
@@ -1096,18 +1100,19 @@ __device__ __forceinline__ void run_market_ovl(const EngineArgs &args, const Ite
             gb[d.L + q] = v.y;
         }
         if (t == 0) {
+            const uint64_t *a = reinterpret_cast<const uint64_t *>(scr + 8);
             cae_state *st = args.state + m;
-            st->last = last;
-            st->prev = prev;
+            st->last = scr[0];
+            st->prev = scr[1];
             st->steps_done = steps0 + args.S;
-            st->n_trade = n_trade;
-            st->sum_vol = sum_vol;
-            st->sum_px = sum_px;
-            st->sum_spread = sum_spread;
-            st->n_spread = n_spread;
-            st->sum_r = sum_r;
-            st->sum_r2 = sum_r2;
-            st->ref2 = ref2;
+            st->n_trade = a[0];
+            st->sum_vol = a[1];
+            st->sum_px = a[2];
+            st->sum_spread = a[3];
+            st->n_spread = a[4];
+            st->sum_r = fs[0];
+            st->sum_r2 = fs[1];
+            st->ref2 = scr[2];
         }
     }
 }
