@@ -376,6 +376,26 @@ def test_overlapped_ragged_markets(cfg):
     _assert_states(st, rst)
 
 
+@pytest.mark.parametrize("L,K,nn,nm", [(256, 16, 1024, 0), (256, 16, 300, 700), (128, 8, 200, 800),
+                                        (64, 4, 100, 900), (200, 30, 500, 500)])
+def test_overlapped_small_books_near_the_edges(L, K, nn, nm):
+    """Overlapped markets with books of up to 4 ticks per lane add the order bins inside the
+    clearing unless the offset window leaves the book; momentum-heavy populations drive the
+    price to the edges, so both ways run, within one market and across steps."""
+    A = 1024
+    descs = W.uniform(12, L, A, K, 50, n_noise=nn, n_mom=nm, h=3)
+    tn = {"waves_per_group": 8, "waves_per_market": {c: 4 for c in range(40)},
+          "overlap": {c: 4 for c in range(40)}}
+    st, bk, _ = _run_gpu(descs, 2024, [70, 33], tuning=tn)
+    rst, rbk, rpr, _ = O.run(descs, 2024, 103, trace=True)
+    _assert_books(descs, bk, rbk)
+    _assert_states(st, rst)
+    if L <= 200:
+        # the trend carried the prices to within K of an edge for some steps and not for others
+        near = (rpr < K) | (rpr > L - 1 - K)
+        assert near.any() and not near.all()
+
+
 def test_overlapped_mixed_with_other_modes():
     """Overlapped, plain lock-step, single-wave and pipelined classes in one launch."""
     rng = np.random.default_rng(19)
