@@ -356,7 +356,7 @@ __device__ __forceinline__ ClearOut clear_wave(uint32_t *__restrict__ bk, uint32
     const uint32_t q0 = lane * TPL;
 
     uint32_t sb = 0, sa = 0;  // this lane's bid and ask totals
-#pragma unroll
+#pragma unroll 2
     for (int c = 0; c < NCH; ++c) {
         uint32_t b[CH], k[CH];
         load_pairs<CH>(bk, q0 + c * CH, b, k);
@@ -376,7 +376,7 @@ __device__ __forceinline__ ClearOut clear_wave(uint32_t *__restrict__ bk, uint32
     uint32_t best = 0, bestq = 0;
     {
         uint32_t cb = eb, ca = ea;
-#pragma unroll
+#pragma unroll 2
         for (int c = 0; c < NCH; ++c) {
             uint32_t b[CH], k[CH];
             load_pairs<CH>(bk, q0 + c * CH, b, k);
@@ -403,7 +403,7 @@ __device__ __forceinline__ ClearOut clear_wave(uint32_t *__restrict__ bk, uint32
     uint32_t hb = kNone, la = kNone;
     {
         uint32_t cb = eb, ca = ea;
-#pragma unroll
+#pragma unroll 2
         for (int c = 0; c < NCH; ++c) {
             uint32_t b[CH], k[CH];
             const uint32_t qc = q0 + c * CH;
