@@ -257,7 +257,7 @@ int cae_clear(uint32_t L, uint32_t M, uint32_t *dev_book, uint32_t *dev_pstar,
  * activations, trained and evaluated on the GPU by bfloat16 matrix-core kernels with fp32
  * accumulation.  It is not part of the paper's method: it maps agent-population parameters to
  * ensemble statistics for the parameter sweeps the paper motivates (section IV-J), with the
- * exact engine above as its fallback and the judge of its error.
+ * exact engine above as its fallback and the reference that measures its error.
  *
  * Parameter layout (fp32, row-major, input index first), P = cae_mlp_sizes().n_params floats:
  *   W1[d_in][H], b1[H], W2[H][H], b2[H], W3[H][d_out], b3[d_out]

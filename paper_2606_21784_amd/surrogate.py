@@ -9,7 +9,7 @@ parameters derived from theta (noise and momentum shares after rounding to agent
 offset half-width K and the integer quantity bound Q, each scaled to [-1, 1]); its outputs are
 the logarithms of the three statistics, centred; it is trained with a Huber loss in log space,
 which matches the relative-error criterion.  The engine remains the fallback (``exact_stats``)
-and the judge of the surrogate's error on held-out parameters.
+and the reference that measures the surrogate's error on held-out parameters.
 """
 import time
 
