@@ -188,23 +188,47 @@ def test_clear_worked_example_and_random_books():
         np.testing.assert_array_equal(dev.cpu().numpy().view(np.uint32).reshape(n, 2, L), rres)
 
 
-def test_fixed_workload_full_parity():
-    """The fixed workload at full size (1024 x 1024 agents x 1000 steps, L = 256) in the launch
-    configuration the benchmark times; every market against the oracle."""
+@pytest.fixture(scope="module")
+def fixed_reference():
     w = W.fixed()
-    st, bk, _ = _run_gpu(w["descs"], w["seed"], [w["S"]])
-    rst, rbk = O.run(w["descs"], w["seed"], w["S"])
+    return w, O.run(w["descs"], w["seed"], w["S"])
+
+
+@pytest.mark.parametrize("schedule", ["autotuned", "default"])
+def test_fixed_workload_full_parity(schedule, fixed_reference):
+    """The fixed workload at full size (1024 x 1024 agents x 1000 steps, L = 256), every market
+    against the oracle: in the launch configuration the benchmark times (the autotuner's
+    schedule, overlapped lock-step on MI355X) and in the default one."""
+    w, (rst, rbk) = fixed_reference
+    tn = None
+    if schedule == "autotuned":
+        _engine()
+        from paper_2606_21784_amd import autotune
+        tn = autotune.tune(w["descs"], seed=w["seed"])
+    st, bk, used = _run_gpu(w["descs"], w["seed"], [w["S"]], tuning=tn)
+    if tn is not None:
+        assert used["waves_per_group"] == tn["waves_per_group"]
+        assert used["overlap"] == tn["overlap"]
     _assert_books(w["descs"], bk, rbk)
     _assert_states(st, rst)
 
 
 @pytest.mark.slow
-def test_market_sweep_sampled():
+def _tuned(descs, seed):
+    _engine()
+    from paper_2606_21784_amd import autotune
+    return autotune.tune(descs, seed=seed)
+
+
+@pytest.mark.parametrize("schedule", ["autotuned", "default"])
+def test_market_sweep_sampled(schedule):
     """Market-count sweep at its full step count (10000 steps, L = 512, A = 4096), smallest
-    and a mid-size M; sampled markets re-simulated alone by the oracle."""
+    and a mid-size M, in the benchmark's autotuned schedule and the default one; sampled
+    markets re-simulated alone by the oracle."""
     for M in (16, 1024):
         w = W.market_sweep(M)
-        st, bk, _ = _run_gpu(w["descs"], w["seed"], [w["S"]])
+        tn = _tuned(w["descs"], w["seed"]) if schedule == "autotuned" else None
+        st, bk, _ = _run_gpu(w["descs"], w["seed"], [w["S"]], tuning=tn)
         ids = [0, M // 2, M - 1]
         rst, rbk = O.run(w["descs"][ids], w["seed"], w["S"], ids=ids)
         _assert_books(w["descs"], bk, rbk, ids=ids)
@@ -212,10 +236,15 @@ def test_market_sweep_sampled():
 
 
 @pytest.mark.slow
-def test_uneven_ensemble_sampled():
+@pytest.mark.parametrize("schedule", ["autotuned", "default"])
+def test_uneven_ensemble_sampled(schedule):
+    """The 8192-market uneven ensemble at full size in the benchmark's autotuned schedule and
+    the default one; sampled markets (the largest and smallest A among them) against the
+    oracle."""
     w = W.uneven()
     d = w["descs"]
-    st, bk, _ = _run_gpu(d, w["seed"], [w["S"]])
+    tn = _tuned(d, w["seed"]) if schedule == "autotuned" else None
+    st, bk, _ = _run_gpu(d, w["seed"], [w["S"]], tuning=tn)
     A = d["A"].astype(np.int64)
     rng = np.random.default_rng(1)
     ids = sorted(set([int(np.argmax(A)), int(np.argmin(A))] +
