@@ -678,7 +678,7 @@ __device__ __forceinline__ void gen_orders(const DevMarket &d, uint32_t m, uint3
 // tick is formed).  Bins, as (bid, ask) pairs: pair o < 2K+1 holds the NOISE orders of offset
 // o - K; pair 2K+1 the MOMENTUM quantities by their coin (the trend decides at the flush whether
 // the coin or the trend picks the side); pair 2K+2 the MAKER quantities by side.  Agents
-// a0, a0 + stride, ... below `end`.
+// b | lane for the row bases b = b0, b0 + stride, ... (multiples of 64), below `end`.
 template <typename Gen>
 __device__ __forceinline__ void gen_rel(const DevMarket &d, uint32_t s, const Gen &gen, uint32_t b0,
                                         uint32_t stride, uint32_t end, uint32_t lane, uint32_t *H)
@@ -965,8 +965,9 @@ __device__ __forceinline__ void run_market(const EngineArgs &args, const Item &i
 // Lock-step market of the last-tick model with the next step's orders generated while the
 // current step clears.  One wave at a time owns the clearing for a block of kOvlBlock steps (the
 // role rotates over the market's waves block by block, which spreads the clearing over the
-// SIMDs): in step i the owner adds the bins of step i to the book at the reference of step
-// i - 1's price, clears it, keeps the step's price and statistics in its registers and then
+// SIMDs): in step i the owner adds the bins of step i to the book around the price after step
+// i - 1 (the reference of step i), clears it, keeps the step's price and statistics in its
+// registers and then
 // generates `share` rows of 64 agents of step i + 1; the other waves generate the rest of step
 // i + 1 into the other bin buffer.  No other wave needs the price: one barrier per step, no LDS
 // round trip for the result, and no wave waits for a clearing.  At the end of its block the
