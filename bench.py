@@ -270,14 +270,15 @@ DYN_P_MKT = 0.05
 def dynamics_leg():
     """The agent-mix sweep of section IV-J (alpha_mom 0..0.70, makers 0.15, 64 markets of each
     mix, 1000 steps, L = 128, K = 8, Q = 10) for A in {16, 64, 256, 1024}: one traced launch
-    of all 3840 markets per agent model, then the stylized facts from the recorded series."""
+    of all 3840 markets per agent model (autotuned schedule), then the stylized facts from the
+    recorded series."""
     from paper_2606_21784_amd import dynamics, engine
     from paper_2606_21784_amd._lib import MODEL_LAST, MODEL_MID
     dynamics.run_sweep(A_values=(16,), alphas=(0.0,), markets=4, S=10)  # load / warm up
     out = {"paper_rtx5090": "12.8e6-event sweep in under 0.25 s (section IV-J)"}
     for name, flags in (("last_tick", engine.model_flags(MODEL_LAST)),
                         ("mid_price_pmkt%.2f" % DYN_P_MKT, engine.model_flags(MODEL_MID, DYN_P_MKT))):
-        report, timing = dynamics.run_sweep(flags=flags)
+        report, timing = dynamics.run_sweep(flags=flags, tuning="auto")
         out[name] = {
             "timing": timing, "facts_A256": dynamics.facts(report, A=256),
             "sweep": {str(A): {k: report[A][k] for k in ("alpha_mom", "tick_change_std",

@@ -114,12 +114,17 @@ def run_sweep(A_values=(16, 64, 256, 1024), alphas=ALPHA_MOM, markets=64, S=1000
               Q=10, seed=6, tuning=None, flags=0):
     """The composition sweep for every population size in A_values, all in one traced launch.
 
-    Returns (report, timing): report[A][key] = list over alphas; timing = launch time and
-    events of the whole sweep."""
+    tuning: a schedule for engine.Ensemble, None for the default one, or "auto" for the
+    autotuner's (probed on untraced launches of the same markets).  Returns (report, timing):
+    report[A][key] = list over alphas; timing = launch time and events of the whole sweep."""
     import torch
     descs = np.concatenate([composition_descs(A, L, K, Q, markets, alphas, flags=flags)
                             for A in A_values])
+    if isinstance(tuning, str) and tuning == "auto":
+        from . import autotune
+        tuning = autotune.tune(descs, seed=seed)
     ens = engine.Ensemble(descs, seed, tuning=tuning)
+    used = ens.tuning()
     opening = torch.from_numpy(ens.read_state()["last"].astype(np.int64)).to(ens.device)
     t0 = time.perf_counter()
     price, volume = ens.step_traced(S)
@@ -145,7 +150,10 @@ def run_sweep(A_values=(16, 64, 256, 1024), alphas=ALPHA_MOM, markets=64, S=1000
     events = float(descs["A"].astype(np.float64).sum()) * S
     timing = {"markets": int(len(descs)), "steps": int(S), "events": events,
               "kernel_ms": kernel_ms, "wall_ms": 1e3 * wall,
-              "events_per_s": events / (kernel_ms * 1e-3)}
+              "events_per_s": events / (kernel_ms * 1e-3),
+              "schedule": {"waves_per_group": used["waves_per_group"],
+                           "waves_per_market": sorted(set(used["waves_per_market"].values())),
+                           "overlap": sorted(set(used["overlap"].values()))}}
     return report, timing
 
 
