@@ -154,10 +154,10 @@ typedef struct cae_tuning {
                                                    current step clears, the clearing wave
                                                    taking k - 1 rows of 64 agents after its
                                                    clearing; 0 = off.  Applies to classes of
-                                                   2 or more waves per market, not pipelined,
-                                                   in ensembles of last-tick markets with the
-                                                   Philox generator; ignored (reported as 0)
-                                                   elsewhere.                               */
+                                                   2 or more waves per market, not pipelined
+                                                   (ignored and reported as 0 elsewhere);
+                                                   markets with K above 1022 (510 for the
+                                                   mid-price model) run plain lock-step.    */
     float class_cost[CAE_NUM_CLASSES];          /* relative cost of one market-step per
                                                    class for the longest-first order;
                                                    0 = the built-in model A + 2*64*TPL    */

@@ -5,9 +5,9 @@ The engine's schedule has these knobs (``cae_tuning`` in include/cae.h):
     one market's orders; the rest of the workgroup's waves belong to other markets;
   * pipelined, per size class: markets run in pairs that share all of a workgroup's waves in
     alternating phases (one wave clears one market while the others generate the other's);
-  * overlap, per size class (lock-step, last-tick ensembles): the market's other waves generate
-    the next step's orders while one wave clears, the clearing wave taking overlap - 1 rows of
-    64 agents after its clearing;
+  * overlap, per size class (lock-step classes, either agent model): the market's other waves
+    generate the next step's orders while one wave clears, the clearing wave taking overlap - 1
+    rows of 64 agents after its clearing;
   * waves per workgroup: how many markets of one class share a workgroup (in lock-step when a
     market spans more than one wave) and therefore how the workgroup's LDS is partitioned into
     market slices;
@@ -191,9 +191,9 @@ def tune(descs, seed=0, S_probe=None, min_markets=None, cache=None, arch="gfx950
 
 
 def overlap_possible(descs):
-    """Whether the engine runs an overlapped schedule for these markets: last-tick agents and the
-    Philox generator in every market (flags 0)."""
-    return bool((descs["flags"] == 0).all())
+    """Whether the engine can run an overlapped schedule for these markets (every agent model
+    and generator can)."""
+    return len(descs) > 0
 
 
 def per_size_groups(descs):

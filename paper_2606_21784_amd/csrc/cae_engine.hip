@@ -752,6 +752,85 @@ __device__ __forceinline__ void flush_rel(const DevMarket &d, uint32_t last, uin
         if (j0 + lane < span + 2u) P[j0 + lane] = make_uint2(0u, 0u);
 }
 
+// Mid-price orders of step s aggregated before the reference 2 mid = 2n + e is known.  A NOISE
+// order's tick floor(mid + K (2 w1 / 2^32 - 1) + 1/2) is n - K + g + c for e = 0 and
+// n - K + g + 1 for e = 1, with g = hi(2K w1) and c = [lo(2K w1) >= 2^31]; it is binned by
+// (u = g + c, c) as pair 2u + c.  After the 2(2K+1) noise pairs: pair 0 marketable NOISE (buys
+// go to the top tick, sells to tick 0), pair 1 MOMENTUM by coin, pair 2 marketable MOMENTUM by
+// coin, pair 3 MAKER by side (section III-C's rules as in order_ctx).
+template <typename Gen>
+__device__ __forceinline__ void gen_rel_mid(const DevMarket &d, uint32_t s, const Gen &gen, uint32_t b0,
+                                            uint32_t stride, uint32_t end, uint32_t lane, uint32_t *H)
+{
+    const uint32_t twoK = 2u * d.K, xb = 2u * (2u * twoK + 2u);  // first extra pair, in words
+    const uint32_t tmkt = (d.flags >> CAE_PMKT_SHIFT) << CAE_PMKT_SHIFT;
+    const uint32_t mom_end = d.n_noise + d.n_mom;
+    for (uint32_t b = b0; b < end; b += stride) {
+        const uint32_t a = b | lane;
+        if (a < end) {
+            uint32_t w0, w1, w2, w3;
+            gen.words4_row(b, lane, w0, w1, w2, w3);
+            const uint32_t side = w0 >> 31;
+            const bool mkt = w3 < tmkt;
+            uint32_t word;
+            if (a < d.n_noise) {
+                const uint64_t x = (uint64_t)twoK * w1;
+                const uint32_t c = (uint32_t)x >> 31, u = (uint32_t)(x >> 32) + c;
+                word = mkt ? xb + side : 2u * (2u * u + c) + side;
+            } else if (a < mom_end) {
+                word = xb + (mkt ? 4u : 2u) + side;
+            } else {
+                word = xb + 6u + ((a ^ s) & 1u);
+            }
+            atomicAdd(&H[word], qty1(w2, d.Q));
+        }
+    }
+}
+
+// Adds the mid-price bins of one step to the book at reference mid2 = 2n + e (momentum
+// direction from mid2 vs mid2p) and clears them.  Lanes: 2(2K+1) noise pairs, then marketable
+// NOISE buys / sells, MOMENTUM buys / sells, marketable MOMENTUM buys / sells, MAKER bids / asks.
+__device__ __forceinline__ void flush_rel_mid(const DevMarket &d, uint32_t mid2, uint32_t mid2p, uint32_t *H,
+                                              uint32_t *bk, uint32_t lane)
+{
+    const uint32_t np = 2u * (2u * d.K + 1u);  // noise pairs
+    const int n = (int)(mid2 >> 1), e = (int)(mid2 & 1u), top = (int)d.L - 1, h = (int)d.h;
+    const bool up = mid2 > mid2p, down = mid2 < mid2p, flat = mid2 == mid2p;
+    uint2 *P = reinterpret_cast<uint2 *>(H);
+    for (uint32_t j0 = 0; j0 < np + 8u; j0 += 64u) {
+        const uint32_t j = j0 + lane;
+        const uint32_t x = j - np;  // 0..7 for the extra lanes
+        const bool noise = j < np;
+        const uint2 v = P[noise ? j : np + min(x >> 1, 3u)];
+        const uint32_t all = v.x + v.y;
+        const uint32_t buys = up ? all : (flat ? v.x : 0u), sells = down ? all : (flat ? v.y : 0u);
+        uint32_t lo = 0, hi = 0;
+        int tick;
+        if (noise) {
+            const int u = (int)(j >> 1), c = (int)(j & 1u);
+            tick = n - (int)d.K + u + (e ? 1 - c : 0);
+            lo = v.x;
+            hi = v.y;
+        } else {
+            switch (x) {
+            case 0: tick = top; lo = v.x; break;            // marketable NOISE buys
+            case 1: tick = 0; hi = v.y; break;              // marketable NOISE sells
+            case 2: tick = n + 1 + e; lo = buys; break;     // MOMENTUM buys at round(mid + 1)
+            case 3: tick = n - 1 + e; hi = sells; break;    // MOMENTUM sells at round(mid - 1)
+            case 4: tick = top; lo = buys; break;           // marketable MOMENTUM buys
+            case 5: tick = 0; hi = sells; break;            // marketable MOMENTUM sells
+            case 6: tick = n - h + e; lo = v.x; break;      // MAKER bids at round(mid - h)
+            default: tick = n + h + e; hi = v.y; break;     // MAKER asks at round(mid + h)
+            }
+        }
+        tick = clamp_tick(tick, top);
+        if (j < np + 8u && (lo | hi) != 0u)
+            atomicAdd(reinterpret_cast<unsigned long long *>(bk) + tick, ((unsigned long long)hi << 32) | lo);
+    }
+    for (uint32_t j0 = 0; j0 < np + 4u; j0 += 64u)
+        if (j0 + lane < np + 4u) P[j0 + lane] = make_uint2(0u, 0u);
+}
+
 // Best bid / best ask (kNone when a side is empty) of an LDS book, by one wave: the reference
 // of the mid-price model at the start of a call (later steps take them from the clearing).
 __device__ __forceinline__ void book_ends(const uint32_t *bk, uint32_t tpl, uint32_t lane, uint32_t &bb,
@@ -1118,6 +1197,177 @@ __device__ __forceinline__ void run_market_ovl(const EngineArgs &args, const Ite
     }
 }
 
+// The same schedule for ensembles that may hold mid-price or SplitMix64 markets (the FULL
+// instantiation): the reference is 2 x mid, tracked as in run_market, and the bins are the
+// model's (gen_rel / gen_rel_mid).  Scratch words 2 and 3 hand over mid2 and mid2p.
+template <int TPL_MAX, bool FULL, bool TRACE>
+__device__ __forceinline__ void run_market_ovl_any(const EngineArgs &args, const Item &item, uint32_t sub,
+                                               uint32_t w_in, uint32_t lane, bool active, uint32_t *lds)
+{
+    const uint32_t wpm_mask = (1u << item.wpm_log2) - 1u;
+    const uint32_t nthr = 64u << item.wpm_log2;
+    const uint32_t t = (w_in << 6) | lane;
+    uint32_t *bk = lds + sub * item.stride;
+    uint32_t *scr = bk + item.stride - kScr;
+    uint32_t *H0 = bk + item.hoff;
+    uint32_t *H1 = H0 + item.hwords;
+    double *fs = reinterpret_cast<double *>(scr + 4);
+
+    uint32_t m = 0;
+    DevMarket d{};
+    uint32_t last = 0, prev = 0, mid2 = 0, mid2p = 0;
+    uint64_t steps0 = 0;
+    double sum_r = 0.0, sum_r2 = 0.0;
+    if (active) {
+        m = args.order[item.first + sub];
+        d = args.desc[m];
+        const cae_state *st = args.state + m;
+        last = st->last;
+        prev = st->prev;
+        steps0 = st->steps_done;
+        mid2p = st->ref2;
+        sum_r = st->sum_r;
+        sum_r2 = st->sum_r2;
+        if (t < 10u) scr[8u + t] = reinterpret_cast<const uint32_t *>(st)[4u + t];  // n_trade .. n_spread
+        const uint32_t *gb = args.book + d.book_off;
+        const uint32_t padded = 64u * d.tpl;
+        for (uint32_t q = t; q < padded; q += nthr) {
+            uint2 v = make_uint2(0u, 0u);
+            if (q < d.L) {
+                v.x = gb[q];
+                v.y = gb[d.L + q];
+            }
+            reinterpret_cast<uint2 *>(bk)[q] = v;
+        }
+        for (uint32_t q = t; q < 2u * item.hwords; q += nthr) H0[q] = 0u;
+    }
+    __syncthreads();
+    const bool mid = FULL && (d.flags & CAE_MODEL_MASK) == CAE_MODEL_MID;
+    const bool smx = FULL && uses_splitmix(d);
+    mid2 = 2u * last;
+    if (FULL && active && mid) {
+        uint32_t bb, ba;
+        book_ends(bk, d.tpl, lane, bb, ba);
+        mid2 = next_mid2(true, bb, ba, last);
+    }
+    if constexpr (FULL) __syncthreads();  // every wave has read the book before orders land
+    if (active) gen_orders<FULL>(d, d.id, (uint32_t)steps0, Refs{last, prev, mid2, mid2p}, args.k0, args.k1, t,
+                                 nthr, bk);
+    __syncthreads();
+
+    const double *lnT = args.lnT + d.L;
+    const uint64_t seed64 = ((uint64_t)args.k1 << 32) | args.k0;
+    // the next step's orders into bin buffer Hn, agents b | lane for b = b0, b0 + stride, ...
+    const auto gen_bins = [&](uint32_t sn, uint32_t b0, uint32_t stride, uint32_t end, uint32_t *Hn) {
+        if constexpr (FULL) {
+            if (smx) {
+                const SplitMixStep g(sn, d.id, d.A, seed64);
+                if (mid) gen_rel_mid(d, sn, g, b0, stride, end, lane, Hn);
+                else gen_rel(d, sn, g, b0, stride, end, lane, Hn);
+                return;
+            }
+            if (mid) {
+                gen_rel_mid(d, sn, PhiloxStep(sn, d.id, args.k0, args.k1), b0, stride, end, lane, Hn);
+                return;
+            }
+        }
+        gen_rel(d, sn, PhiloxStep(sn, d.id, args.k0, args.k1), b0, stride, end, lane, Hn);
+    };
+    uint64_t n_trade = 0, sum_vol = 0, sum_px = 0, sum_spread = 0, n_spread = 0;  // this wave's steps
+    const uint32_t own = min(d.A, item.share * 64u);        // agents of the clearing wave
+    const uint32_t ostride = nthr - 64u;                   // the other waves' stride
+    for (uint32_t i = 0; i < args.S; ++i) {
+        const uint32_t s = (uint32_t)steps0 + i;
+        const uint32_t c = (i >> kOvlBlockLog2) & wpm_mask;
+        uint32_t *Hn = (i & 1u) ? H0 : H1;  // bins of step i + 1
+        const bool more = i + 1u < args.S;
+        if (active && w_in == c) {
+            __builtin_amdgcn_s_setprio(3);
+            if (i != 0u && (i & (kOvlBlock - 1u)) == 0u) {  // first step of this wave's block
+                const uint4 h = *reinterpret_cast<const uint4 *>(scr);
+                last = (uint32_t)__builtin_amdgcn_readfirstlane((int)h.x);
+                prev = (uint32_t)__builtin_amdgcn_readfirstlane((int)h.y);
+                mid2 = (uint32_t)__builtin_amdgcn_readfirstlane((int)h.z);
+                mid2p = (uint32_t)__builtin_amdgcn_readfirstlane((int)h.w);
+                sum_r = fs[0];
+                sum_r2 = fs[1];
+            }
+            if (i >= 1u) {
+                if (FULL && mid) flush_rel_mid(d, mid2, mid2p, (i & 1u) ? H1 : H0, bk, lane);
+                else flush_rel(d, last, prev, (i & 1u) ? H1 : H0, bk, lane);
+            }
+            wave_sync();
+            const ClearOut co = clear_dispatch<TPL_MAX>(bk, d.tpl, lane);
+            if (co.v != 0) {
+                n_trade += 1;
+                sum_vol += co.v;
+                sum_px += co.p;
+            }
+            if (co.bb != kNone && co.ba != kNone) {
+                sum_spread += (uint64_t)(co.ba - co.bb);
+                n_spread += 1;
+            }
+            prev = last;
+            if (co.v != 0) last = co.p;
+            mid2p = mid2;
+            mid2 = next_mid2(mid, co.bb, co.ba, last);
+            if constexpr (TRACE) {
+                if (lane == 0) trace_step(args, m, i, last, co.v);
+            }
+            // the log-table loads are issued here and consumed after the wave's rows
+            const double x = lnT[last] - lnT[prev];
+            if (more) gen_bins(s + 1u, 0u, 64u, own, Hn);
+            sum_r = sum_r + x;
+            sum_r2 = sum_r2 + x * x;
+            if (((i + 1u) & (kOvlBlock - 1u)) == 0u || !more) {  // hand over (or finish)
+                if (lane == 0) {
+                    *reinterpret_cast<uint4 *>(scr) = make_uint4(last, prev, mid2, mid2p);
+                    fs[0] = sum_r;
+                    fs[1] = sum_r2;
+                }
+            }
+            __builtin_amdgcn_s_setprio(0);
+        } else if (active && more) {
+            const uint32_t r = (w_in - c - 1u) & wpm_mask;  // 0 .. wpm - 2
+            gen_bins(s + 1u, own + (r << 6), ostride, d.A, Hn);
+        }
+        __syncthreads();
+    }
+    // every wave adds the integer totals of the steps it cleared
+    if (active && lane == 0) {
+        unsigned long long *a = reinterpret_cast<unsigned long long *>(scr + 8);
+        atomicAdd(a + 0, (unsigned long long)n_trade);
+        atomicAdd(a + 1, (unsigned long long)sum_vol);
+        atomicAdd(a + 2, (unsigned long long)sum_px);
+        atomicAdd(a + 3, (unsigned long long)sum_spread);
+        atomicAdd(a + 4, (unsigned long long)n_spread);
+    }
+    __syncthreads();
+    if (active) {
+        uint32_t *gb = args.book + d.book_off;
+        for (uint32_t q = t; q < d.L; q += nthr) {
+            const uint2 v = reinterpret_cast<const uint2 *>(bk)[q];
+            gb[q] = v.x;
+            gb[d.L + q] = v.y;
+        }
+        if (t == 0) {
+            const uint64_t *a = reinterpret_cast<const uint64_t *>(scr + 8);
+            cae_state *st = args.state + m;
+            st->last = scr[0];
+            st->prev = scr[1];
+            st->steps_done = steps0 + args.S;
+            st->n_trade = a[0];
+            st->sum_vol = a[1];
+            st->sum_px = a[2];
+            st->sum_spread = a[3];
+            st->n_spread = a[4];
+            st->sum_r = fs[0];
+            st->sum_r2 = fs[1];
+            st->ref2 = scr[3];
+        }
+    }
+}
+
 // Scratch layout of a pipelined market (32-bit words): 0 last, 1 prev, 2-3 steps at item start,
 // 4-5 n_trade, 6-7 sum_vol, 8-9 sum_px, 10-11 sum_spread, 12-13 n_spread, 14-15 sum_r,
 // 16-17 sum_r2, 18 ref2 (2 x the previous step's reference), 19 reserved (words 0-19 are the
@@ -1321,8 +1571,9 @@ __global__ void __launch_bounds__(1024) cae_engine_kernel(const EngineArgs args)
             run_pair<TPL_MAX, FULL, TRACE>(args, item, wave, lane, blockDim.x >> 6, lds);
         } else if (item.wpm_log2 == 0) {
             if (active) run_market<TPL_MAX, false, FULL, TRACE>(args, item, sub, w_in, lane, true, lds);
-        } else if (!FULL && item.pipe == 2u) {
-            run_market_ovl<TPL_MAX, TRACE>(args, item, sub, w_in, lane, active, lds);
+        } else if (item.pipe == 2u) {
+            if constexpr (FULL) run_market_ovl_any<TPL_MAX, true, TRACE>(args, item, sub, w_in, lane, active, lds);
+            else run_market_ovl<TPL_MAX, TRACE>(args, item, sub, w_in, lane, active, lds);
         } else {
             run_market<TPL_MAX, true, FULL, TRACE>(args, item, sub, w_in, lane, active, lds);
         }
@@ -1515,11 +1766,12 @@ uint32_t tpl_for(uint32_t L)
 
 // Words of one order-bin buffer of an overlapped market: 2K + 3 (bid, ask) pairs, rounded up to
 // a power of two of at least 64 so that markets of nearby K share items.
-constexpr uint32_t kMaxOverlapK = 1022;
-uint32_t hwords_for(uint32_t K)
+constexpr uint32_t kMaxOverlapK = 1022, kMaxOverlapKMid = 510;
+uint32_t hwords_for(uint32_t K, bool mid)
 {
+    const uint32_t need = mid ? 8u * K + 12u : 4u * K + 6u;  // last-tick: 2K + 3 pairs; mid: 4K + 6
     uint32_t w = 64;
-    while (w < 4u * K + 6u) w <<= 1;
+    while (w < need) w <<= 1;
     return w;
 }
 
@@ -1660,7 +1912,6 @@ int build_schedule(cae_ensemble *e, const cae_tuning *tn, const uint32_t *ids,
     for (uint32_t m = 0; m < M; ++m)
         e->any_mid |= (e->desc[m].flags & CAE_MODEL_MASK) == CAE_MODEL_MID ||
                       ((e->desc[m].flags >> CAE_GEN_SHIFT) & 0xFFu) == CAE_GEN_SPLITMIX;
-    if (e->any_mid) std::memset(t.overlap, 0, sizeof(t.overlap));
     for (uint32_t m = 0; m < M; ++m) {
         const cae_market &d = e->desc[m];
         const uint32_t c = lclass(d.L) * 8u + aclass(d.A);
@@ -1671,7 +1922,7 @@ int build_schedule(cae_ensemble *e, const cae_tuning *tn, const uint32_t *ids,
         if (t.pipelined[c]) w = 1;  // a pipelined pair uses the whole workgroup
         wpm[m] = w;
         t.waves_per_market[c] = (uint8_t)w;
-        if (w < 2 || e->any_mid) t.overlap[c] = 0;
+        if (w < 2) t.overlap[c] = 0;
         wpm_max = std::max(wpm_max, w);
         tpl_max = std::max(tpl_max, tpl_for(d.L));
     }
@@ -1708,11 +1959,12 @@ int build_schedule(cae_ensemble *e, const cae_tuning *tn, const uint32_t *ids,
         const uint32_t m = order[idx];
         const uint32_t w = wpm[m], tp = tpl_for(e->desc[m].L);
         const uint32_t c = lclass(e->desc[m].L) * 8u + aclass(e->desc[m].A);
-        // overlapped markets keep 2 x (2K + 3) bin pairs in LDS; wider offset ranges run plain
-        const uint32_t ov = e->desc[m].K <= kMaxOverlapK ? t.overlap[c] : 0u;
+        // overlapped markets keep two buffers of bins in LDS; wider offset ranges run plain
+        const bool mid = (e->desc[m].flags & CAE_MODEL_MASK) == CAE_MODEL_MID;
+        const uint32_t ov = e->desc[m].K <= (mid ? kMaxOverlapKMid : kMaxOverlapK) ? t.overlap[c] : 0u;
         const uint32_t pp = t.pipelined[c] ? 1u : (ov ? 2u : 0u);
         const uint32_t share = ov ? ov - 1u : 0u;
-        const uint32_t hw = ov ? hwords_for(e->desc[m].K) : 0u;
+        const uint32_t hw = ov ? hwords_for(e->desc[m].K, mid) : 0u;
         const uint32_t stride = 2u * 64u * tp + 2u * hw + kScr;
         uint32_t cap = pp == 1u ? 2u : G / w;
         cap = std::max(1u, std::min(cap, lds_budget / (stride * 4u)));

@@ -450,17 +450,24 @@ def test_overlapped_mixed_with_other_modes():
     _assert_states(st, rst)
 
 
-def test_overlap_is_ignored_for_mid_price_ensembles():
-    """The overlap applies to last-tick ensembles only; a mid-price market in the ensemble turns
-    it off (reported as 0) and the results stay exact."""
+@pytest.mark.parametrize("k", [1, 3, 9])
+def test_overlap_with_mid_price_and_splitmix_markets(k):
+    """The overlapped schedule with last-tick and mid-price markets (marketable orders
+    included), Philox and SplitMix64 generators, side by side; mid-price markets with K past
+    510 run plain lock-step.  Exact against the oracle."""
+    mid, smx = O.model_flags(O.MODEL_MID, 3000), O.model_flags(O.MODEL_LAST, 0, O.GEN_SPLITMIX)
     d = np.concatenate([W.uniform(3, 128, 600, 8, 10, n_noise=300, n_mom=200, h=2),
-                        W.uniform(3, 128, 600, 8, 10, n_noise=300, n_mom=200, h=2,
-                                  flags=O.model_flags(O.MODEL_MID, 3000))])
-    tn = {"waves_per_group": 4, "waves_per_market": {c: 4 for c in range(40)},
-          "overlap": {c: 2 for c in range(40)}}
-    st, bk, used = _run_gpu(d, 5, [20], tuning=tn)
-    assert used["overlap"] == {}
-    rst, rbk = O.run(d, 5, 20)
+                        W.uniform(3, 128, 600, 8, 10, n_noise=300, n_mom=200, h=2, flags=mid),
+                        W.uniform(2, 128, 600, 8, 10, n_noise=300, n_mom=200, h=2, flags=smx),
+                        W.uniform(2, 128, 600, 8, 10, n_noise=300, n_mom=200, h=2,
+                                  flags=O.model_flags(O.MODEL_MID, 20000, O.GEN_SPLITMIX)),
+                        W.uniform(2, 1024, 700, 600, 10, n_noise=300, n_mom=200, h=2, flags=mid),
+                        W.uniform(2, 200, 900, 0, 7, n_noise=500, n_mom=300, h=1, flags=mid)])
+    tn = {"waves_per_group": 8, "waves_per_market": {c: 4 for c in range(40)},
+          "overlap": {c: k for c in range(40)}}
+    st, bk, used = _run_gpu(d, 5, [20, 1, 9], tuning=tn)
+    assert set(used["overlap"].values()) == {k}
+    rst, rbk = O.run(d, 5, 30)
     _assert_books(d, bk, rbk)
     _assert_states(st, rst)
 
@@ -573,7 +580,7 @@ def _mid(p_mkt):
     return O.model_flags(O.MODEL_MID, int(round(p_mkt * 65536)))
 
 
-@pytest.mark.parametrize("mode", ["lockstep", "single", "pipelined"])
+@pytest.mark.parametrize("mode", ["lockstep", "single", "pipelined", "overlapped"])
 @pytest.mark.parametrize("p_mkt", [0.0, 0.05, 0.6])
 def test_mid_model_matches_oracle(mode, p_mkt):
     """The mid-price agent model (section III-C's rules, marketable orders with P_mkt): books,
@@ -618,7 +625,8 @@ def test_models_mixed_in_one_launch():
     cls = [E.size_class(int(a), int(b)) for a, b in zip(L, A)]
     tn = {"waves_per_group": 8,
           "waves_per_market": {c: (1 if c % 3 == 0 else 4) for c in set(cls)},
-          "pipelined": {c: 1 for c in set(cls) if c % 3 == 1}}
+          "pipelined": {c: 1 for c in set(cls) if c % 3 == 1},
+          "overlap": {c: 1 + c % 4 for c in set(cls) if c % 3 == 2}}
     st, bk, _ = _run_gpu(d, 41, [11, 19], tuning=tn)
     rst, rbk = O.run(d, 41, 30)
     _assert_books(d, bk, rbk)
@@ -653,15 +661,17 @@ def test_mid_model_many_launch_starts():
     d["n_mom"] = A // 3
     d["h"] = 2
     d["flags"] = _mid(0.05)
-    for G, wpm in ((16, 4), (8, 2), (4, 4)):
+    for G, wpm, k in ((16, 4, 0), (8, 2, 0), (4, 4, 0), (8, 4, 2), (16, 8, 1)):
         tn = {"waves_per_group": G, "waves_per_market": {c: wpm for c in range(40)}}
+        if k:
+            tn["overlap"] = {c: k for c in range(40)}
         st, bk, _ = _run_gpu(d, 53, [3] * 12 + [5], tuning=tn)
         rst, rbk = O.run(d, 53, 41)
         _assert_books(d, bk, rbk)
         _assert_states(st, rst)
 
 
-@pytest.mark.parametrize("mode", ["lockstep", "single", "pipelined"])
+@pytest.mark.parametrize("mode", ["lockstep", "single", "pipelined", "overlapped"])
 @pytest.mark.parametrize("model", ["last", "mid"])
 def test_splitmix_generator_matches_oracle(mode, model):
     """Markets that select the SplitMix64 generator (section III-G) give the oracle's books,
