@@ -35,11 +35,12 @@ def pooled(states, S_total):
 
 
 def exact_stats(theta, draw_ids, seed=workloads.CALIB_SEED, S=workloads.CALIB_S,
-                markets_per_draw=workloads.CALIB_MARKETS, chunk_draws=8192, timing=None):
+                markets_per_draw=workloads.CALIB_MARKETS, chunk_draws=8192, timing=None, tuning=None):
     """Exact statistics of every parameter row (the engine, one launch per chunk).
 
     theta: (n, 4); draw_ids: (n,) global draw index of each row (market index of replica r of
     draw d is d * markets_per_draw + r, so any subset reproduces the full sweep's markets).
+    tuning: the engine's schedule (see ``sweep_tuning``), None for the default one.
     Returns (n, 3) float64.  If timing is a list, the kernel milliseconds of each launch are
     appended to it."""
     theta = np.atleast_2d(theta)
@@ -50,7 +51,7 @@ def exact_stats(theta, draw_ids, seed=workloads.CALIB_SEED, S=workloads.CALIB_S,
         ids = draw_ids[c0:c0 + chunk_draws]
         d = workloads.calibration_markets(th, markets_per_draw=markets_per_draw)
         mids = (ids[:, None] * markets_per_draw + np.arange(markets_per_draw)[None, :]).ravel()
-        ens = engine.Ensemble(d, seed, market_ids=mids.astype(np.uint32))
+        ens = engine.Ensemble(d, seed, market_ids=mids.astype(np.uint32), tuning=tuning)
         ens.step(S)
         if timing is not None:
             timing.append(ens.last_step_ms())
@@ -58,6 +59,23 @@ def exact_stats(theta, draw_ids, seed=workloads.CALIB_SEED, S=workloads.CALIB_S,
         ens.close()
         out[c0:c0 + len(th)] = pooled_rows(st.reshape(len(th), markets_per_draw), S)
     return out
+
+
+def sweep_tuning(seed=workloads.CALIB_SEED, markets_per_draw=workloads.CALIB_MARKETS, n_probe=4096):
+    """The autotuner's schedule for the calibration sweep's markets (one size class: L = 256,
+    A = 1024), probed on a chunk of draws; the exact sweep runs in it."""
+    from . import autotune
+    theta = workloads.calibration_params(n_probe, seed=6)
+    d = workloads.calibration_markets(theta, markets_per_draw=markets_per_draw)
+    return autotune.tune(d, seed=seed)
+
+
+def _schedule_summary(tn):
+    if not tn:
+        return "default"
+    return {"waves_per_group": tn.get("waves_per_group"),
+            "waves_per_market": sorted(set(tn.get("waves_per_market", {}).values())),
+            "overlap": sorted(set(tn.get("overlap", {}).values()))}
 
 
 def pooled_rows(states, S_total):
@@ -156,17 +174,19 @@ def generate(n_draws=65536, markets_per_draw=workloads.CALIB_MARKETS, S=workload
     theta = workloads.calibration_params(n_draws)
     ids = np.arange(n_draws)
     tr, te = workloads.test_split(n_draws)
+    tn = sweep_tuning(seed, markets_per_draw)
     t0 = time.perf_counter()
-    Ytr = exact_stats(theta[tr], ids[tr], seed, S, markets_per_draw)
+    Ytr = exact_stats(theta[tr], ids[tr], seed, S, markets_per_draw, tuning=tn)
     gen_s = time.perf_counter() - t0
     kern = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    Yte = exact_stats(theta[te], ids[te], seed, S, markets_per_draw, timing=kern)
+    Yte = exact_stats(theta[te], ids[te], seed, S, markets_per_draw, timing=kern, tuning=tn)
     exact_wall = time.perf_counter() - t0
     return {"theta": theta, "ids": ids, "tr": tr, "te": te, "Ytr": Ytr, "Yte": Yte,
             "markets_per_draw": markets_per_draw, "S": S, "seed": seed, "generate_train_s": gen_s,
-            "exact_test_sweep_s": sum(kern) * 1e-3, "exact_test_sweep_wall_s": exact_wall}
+            "exact_test_sweep_s": sum(kern) * 1e-3, "exact_test_sweep_wall_s": exact_wall,
+            "tuning": tn}
 
 
 def fit_and_evaluate(data, epochs=300, hidden=256, batch=1024, lr=3e-3, huber_delta=0.05, noise_draws=256,
@@ -196,7 +216,7 @@ def fit_and_evaluate(data, epochs=300, hidden=256, batch=1024, lr=3e-3, huber_de
     te_ok = te[ok_te]
     sub = np.arange(min(noise_draws, len(te_ok)))
     Yalt = exact_stats(theta[te_ok[sub]], ids[te_ok[sub]], data["seed"] + 1000, data["S"],
-                       data["markets_per_draw"])
+                       data["markets_per_draw"], tuning=data.get("tuning"))
     noise = rel_err(Yalt, Yte[ok_te][sub])
     # surrogate sweep of the held-out parameters (device resident; events on its stream)
     xd = torch.from_numpy(Xte).to(net.device)
@@ -215,6 +235,7 @@ def fit_and_evaluate(data, epochs=300, hidden=256, batch=1024, lr=3e-3, huber_de
         "dropped_draws": int((~ok_tr).sum() + (~ok_te).sum()),
         "exact_test_sweep_s": data["exact_test_sweep_s"],
         "exact_test_sweep_wall_s": data["exact_test_sweep_wall_s"],
+        "exact_schedule": _schedule_summary(data.get("tuning")),
         "surrogate_test_sweep_s": sur_s, "speedup": data["exact_test_sweep_s"] / sur_s,
         "test_events": float(len(te) * data["markets_per_draw"] * workloads.CALIB_A * data["S"]),
         "surrogate_rel_err": summary(err),
@@ -253,7 +274,8 @@ def calibration_demo(net, scaler, data, n_targets=16, n_candidates=65536, verify
         t0 = time.perf_counter()
         P = scaler.inv(net.predict(Xc).cpu().numpy())
         best = np.argsort(_log_dist(P, Yt[None, :]))[:verify]
-        Yv = exact_stats(cand[best], base + best, data["seed"], data["S"], data["markets_per_draw"])
+        Yv = exact_stats(cand[best], base + best, data["seed"], data["S"], data["markets_per_draw"],
+                         tuning=data.get("tuning"))
         dv = _log_dist(Yv, Yt[None, :])
         t_budget = time.perf_counter() - t0
         sur_d.append(float(dv.min()))
@@ -262,7 +284,8 @@ def calibration_demo(net, scaler, data, n_targets=16, n_candidates=65536, verify
         n, best_exact = verify, np.inf
         while True:
             t0 = time.perf_counter()
-            Ye = exact_stats(cand[:n], base + np.arange(n), data["seed"], data["S"], data["markets_per_draw"])
+            Ye = exact_stats(cand[:n], base + np.arange(n), data["seed"], data["S"], data["markets_per_draw"],
+                             tuning=data.get("tuning"))
             dt = time.perf_counter() - t0
             if dt > t_budget and n > verify:
                 break
