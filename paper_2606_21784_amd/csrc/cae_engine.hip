@@ -215,17 +215,6 @@ __device__ __forceinline__ void wave_scan_add2(uint32_t &x, uint32_t &y)
     y += dpp<0x143, 0xc>(y);
 }
 
-__device__ __forceinline__ uint32_t wave_max(uint32_t x)  // uniform result
-{
-    x = max(x, dpp<0x111, 0xf>(x));
-    x = max(x, dpp<0x112, 0xf>(x));
-    x = max(x, dpp<0x114, 0xf>(x));
-    x = max(x, dpp<0x118, 0xf>(x));
-    x = max(x, dpp<0x142, 0xa>(x));
-    x = max(x, dpp<0x143, 0xc>(x));
-    return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
-}
-
 __device__ __forceinline__ uint32_t readlane(uint32_t x, uint32_t l)
 {
     return (uint32_t)__builtin_amdgcn_readlane((int)x, (int)l);
@@ -278,6 +267,21 @@ __device__ __forceinline__ void store_pairs(uint32_t *bk, uint32_t q, const uint
     }
 }
 
+// Clearing price and volume without a cross-lane reduction.  D falls and S rises with the tick,
+// so V = min(D, S) follows S up to the first tick qc with S(qc) >= D(qc) and follows D from there
+// on: V* = max(S(qc - 1), D(qc)), or S of the top tick when no tick crosses.  A lane whose ticks
+// start at q0 takes the candidate max(S(q0 - 1), max over its ticks of V), which equals V* in the
+// lane holding qc (and in the top lane when nothing crosses); that lane is the first whose top
+// tick has S >= D.  The lowest tick reaching V* is the lowest tick with S >= V* (before qc V is
+// S, and when V* = D(qc) > S(qc - 1) the first tick with S >= V* is qc itself), so it is found
+// the same way: in the first lane whose top tick has S >= V*, at that lane's count of ticks with
+// S < V*.  crossing_lane returns the first lane where a predicate that holds on a suffix of the
+// lanes is true, or 63 when it is true nowhere.
+__device__ __forceinline__ uint32_t crossing_lane(bool pred)
+{
+    return (uint32_t)__builtin_ctzll(ballot(pred) | (1ull << 63));
+}
+
 // Clearing of a book of at most 4 ticks per lane, its ticks held in registers throughout: the
 // demand D and supply S of every tick are formed once, the volume pass and the fill reuse them,
 // and the fill takes running minima with V*: fill_b(q) = min(D(q), V*) - min(D(q+1), V*),
@@ -306,20 +310,18 @@ __device__ __forceinline__ ClearOut clear_small(uint32_t *__restrict__ bk, uint3
         D[j + 1] = D[j] - b[j];
         Sq[j] = (j ? Sq[j - 1] : Sb) + k[j];
     }
-    uint32_t best = min(D[0], Sq[0]), bj = 0;
+    uint32_t vc = Sb;
 #pragma unroll
-    for (int j = 1; j < TPL; ++j) {
-        const uint32_t V = min(D[j], Sq[j]);
-        if (V > best) {
-            best = V;
-            bj = (uint32_t)j;
-        }
-    }
+    for (int j = 0; j < TPL; ++j) vc = max(vc, min(D[j], Sq[j]));
     ClearOut out;
-    out.v = wave_max(best);
-    out.p = 0;
-    if (out.v != 0) out.p = readlane(q0 + bj, (uint32_t)__builtin_ctzll(ballot(best == out.v)));
+    out.v = readlane(vc, crossing_lane(Sq[TPL - 1] >= D[TPL - 1]));
     const uint32_t vs = out.v;
+    {
+        uint32_t pj = q0;
+#pragma unroll
+        for (int j = 0; j < TPL; ++j) pj += Sq[j] < vs ? 1u : 0u;
+        out.p = readlane(pj, crossing_lane(Sq[TPL - 1] >= vs));
+    }
     uint32_t md = min(D[0], vs), ms = min(Sb, vs);
 #pragma unroll
     for (int j = 0; j < TPL; ++j) {
@@ -372,8 +374,9 @@ __device__ __forceinline__ ClearOut clear_wave(uint32_t *__restrict__ bk, uint32
     const uint32_t eb = ib - sb;          // bids on ticks below this lane's first tick
     const uint32_t ea = ia - sa;          // asks on ticks below this lane's first tick
 
-    // V(q) = min(D(q), S(q)); D(q) = Tb - bids below q; S(q) = asks at or below q
-    uint32_t best = 0, bestq = 0;
+    // V(q) = min(D(q), S(q)); D(q) = Tb - bids below q; S(q) = asks at or below q.  The lane's
+    // crossing-point candidate (see crossing_lane), and D of its top tick.
+    uint32_t vc = ea, dtop = 0;
     {
         uint32_t cb = eb, ca = ea;
 #pragma unroll 2
@@ -382,25 +385,20 @@ __device__ __forceinline__ ClearOut clear_wave(uint32_t *__restrict__ bk, uint32
             load_pairs<CH>(bk, q0 + c * CH, b, k);
 #pragma unroll
             for (int j = 0; j < CH; ++j) {
-                const uint32_t D = Tb - cb;
+                dtop = Tb - cb;
                 ca += k[j];
-                const uint32_t V = min(D, ca);
-                if (V > best) {
-                    best = V;
-                    bestq = q0 + c * CH + j;
-                }
+                vc = max(vc, min(dtop, ca));
                 cb += b[j];
             }
         }
     }
     ClearOut out;
-    out.v = wave_max(best);
-    out.p = 0;
-    if (out.v != 0) out.p = readlane(bestq, (uint32_t)__builtin_ctzll(ballot(best == out.v)));
+    out.v = readlane(vc, crossing_lane(ia >= dtop));  // ia: S of the lane's top tick
 
-    // closed-form price-priority fill (all zero when V* = 0), then best bid / best ask
+    // closed-form price-priority fill (all zero when V* = 0), then best bid / best ask; the
+    // clearing tick is the lowest tick with S >= V*
     const uint32_t vs = out.v;
-    uint32_t hb = kNone, la = kNone;
+    uint32_t hb = kNone, la = kNone, pj = q0;
     {
         uint32_t cb = eb, ca = ea;
 #pragma unroll 2
@@ -419,6 +417,7 @@ __device__ __forceinline__ ClearOut clear_wave(uint32_t *__restrict__ bk, uint32
                 ca = Sq;
                 b[j] -= fb;
                 k[j] -= fs;
+                pj += Sq < vs ? 1u : 0u;
                 changed |= (fb | fs) != 0;
                 if (b[j] != 0) hb = qc + j;
                 if (k[j] != 0 && la == kNone) la = qc + j;
@@ -426,6 +425,7 @@ __device__ __forceinline__ ClearOut clear_wave(uint32_t *__restrict__ bk, uint32
             if (changed) store_pairs<CH>(bk, qc, b, k);
         }
     }
+    out.p = readlane(pj, crossing_lane(ia >= vs));
     const uint64_t mb = ballot(hb != kNone);
     const uint64_t ma = ballot(la != kNone);
     out.bb = mb ? readlane(hb, 63u - (uint32_t)__builtin_clzll(mb)) : kNone;
