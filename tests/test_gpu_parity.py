@@ -188,6 +188,84 @@ def test_clear_worked_example_and_random_books():
         np.testing.assert_array_equal(dev.cpu().numpy().view(np.uint32).reshape(n, 2, L), rres)
 
 
+def _structured_books(L, rng):
+    """Books built to land the crossing of D and S on chosen ticks: at the edges of the ticks
+    a lane owns, at the first and last tick, nowhere (the top tick's bids exceed every ask),
+    with ties over a plateau of ticks, separated (nothing trades) and one-sided books, and a
+    few large quantities.  Returns (n, 2, L) uint32."""
+    tpl = 1
+    while 64 * tpl < L:
+        tpl *= 2
+    edges = sorted({q for e in range(0, L + 1, tpl) for q in (e - 1, e, e + 1) if 0 <= q < L})
+    out = []
+
+    def book():
+        return np.zeros((2, L), np.uint64)
+
+    for q in edges:
+        # asks up to q, bids from q: the crossing at q with S(q-1) below, equal to and above D(q)
+        for below in (0, 1, 2):
+            b = book()
+            b[1, : q + 1] = 3
+            b[0, q:] = 2
+            b[0, q] += below * 3 * q
+            out.append(b)
+        b = book()  # a plateau: V is the same on every tick of [q, top]
+        b[0, L - 1] = 7
+        b[1, q] = 7
+        out.append(b)
+        b = book()  # separated: every bid below every ask, nothing trades
+        b[0, :q] = 5
+        b[1, q:] = 5
+        out.append(b)
+    for _ in range(4):
+        b = book()  # no crossing below the top tick: its bids exceed all asks
+        b[1, : L] = rng.integers(0, 4, L)
+        b[0, L - 1] = b[1].sum() + 1 + rng.integers(0, 3)
+        out.append(b)
+        b = book()  # crossing at the first tick: its asks exceed all bids
+        b[0, :] = rng.integers(0, 4, L)
+        b[1, 0] = b[0].sum() + rng.integers(0, 3)
+        out.append(b)
+    for side in (0, 1):
+        b = book()
+        b[side] = rng.integers(0, 9, L)
+        out.append(b)
+    for _ in range(40):
+        b = book()  # sparse: a few ticks per side, often on lane edges, some large quantities
+        for side in (0, 1):
+            k = int(rng.integers(1, 5))
+            pool = edges if rng.random() < 0.5 else list(range(L))
+            qs = rng.choice(pool, size=k)
+            big = (1 << 31) // (4 * max(1, k))
+            b[side, qs] += rng.choice([1, 2, 5, big], size=k).astype(np.uint64)
+        out.append(b)
+    books = np.stack(out)
+    assert books.sum(axis=2).max() < (1 << 32)
+    return books.astype(np.uint32)
+
+
+def test_clear_structured_books():
+    """cae_clear on books whose crossing of demand and supply falls on lane edges, on the first
+    and last tick or nowhere, with ties and with nothing to trade, for every ticks-per-lane
+    width, against the oracle."""
+    import torch
+    E = _engine()
+    rng = np.random.default_rng(12)
+    for L in (1, 2, 63, 64, 65, 127, 128, 129, 255, 256, 257, 512, 700, 1023, 1024):
+        books = _structured_books(L, rng)
+        n = books.shape[0]
+        rp, rv, rres = O.clear_batch(books)
+        dev = torch.from_numpy(books.reshape(-1).view(np.int32).copy()).cuda()
+        ps, vs = E.clear_books(dev, L, n)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(ps.cpu().numpy().view(np.uint32), rp, err_msg="L=%d" % L)
+        np.testing.assert_array_equal(vs.cpu().numpy().view(np.uint32).astype(np.uint64), rv,
+                                      err_msg="L=%d" % L)
+        np.testing.assert_array_equal(dev.cpu().numpy().view(np.uint32).reshape(n, 2, L), rres,
+                                      err_msg="L=%d" % L)
+
+
 @pytest.fixture(scope="module")
 def fixed_reference():
     w = W.fixed()
