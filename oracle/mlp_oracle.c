@@ -2,7 +2,7 @@
  * mlp_oracle.c -- TEST INFRASTRUCTURE ONLY.
  *
  * Plain f64 reference of the surrogate network (a multilayer perceptron d_in -> H -> H -> d_out
- * with SiLU hidden activations) used to judge the GPU's bfloat16 matrix-core kernels.  The
+ * with SiLU hidden activations) that the GPU's bfloat16 matrix-core kernels are checked against.  The
  * surrogate is not in the paper; it maps agent-population parameters to ensemble statistics
  * for calibration sweeps (the paper's parameter-sweep use case, section IV-J).
  *

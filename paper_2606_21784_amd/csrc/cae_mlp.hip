@@ -3,7 +3,7 @@
 // The surrogate is a multilayer perceptron d_in -> H -> H -> d_out with SiLU hidden activations
 // that maps agent-population parameters to ensemble statistics.  It is not part of the paper's
 // method; it accelerates the parameter sweeps the paper motivates (section IV-J) and the exact
-// engine stays its fallback and its judge.
+// engine stays its fallback and the reference that measures its error.
 //
 // Precision: weights, inputs, hidden activations and back-propagated gradients are stored in
 // bfloat16 (round to nearest even); every product is accumulated in fp32 by

@@ -191,7 +191,7 @@ def generate(n_draws=65536, markets_per_draw=workloads.CALIB_MARKETS, S=workload
 
 def fit_and_evaluate(data, epochs=300, hidden=256, batch=1024, lr=3e-3, huber_delta=0.05, noise_draws=256,
                      log=None):
-    """Train on the training draws, judge the held-out draws against their exact statistics,
+    """Train on the training draws, score the held-out draws against their exact statistics,
     compare with predictors that use no network, and time the surrogate's held-out sweep."""
     import torch
     from . import mlp

@@ -1,5 +1,5 @@
 """Calibration surrogate end to end at a reduced size: the engine generates the sweep, the
-project's kernels train the network, the engine judges it.  The network must beat the
+project's kernels train the network, the engine scores it.  The network must beat the
 predictors that use no network, and the engine's pooled statistics must equal the oracle's."""
 import numpy as np
 import pytest
