@@ -130,6 +130,27 @@ def test_step_split_and_resume():
     ens2.close()
 
 
+@pytest.mark.parametrize("tuning", [None, {"waves_per_group": 4, "waves_per_market": {c: 4 for c in range(40)},
+                                     "overlap": {c: 4 for c in range(40)}}])
+def test_zero_steps_and_single_market(tuning):
+    """A single market, and cae_step(0), which must leave books and states untouched (also
+    between launches that continue the same market)."""
+    E = _engine()
+    descs = W.uniform(1, 256, 1024, 16, 100)
+    ens = E.Ensemble(descs, 21, tuning=tuning)
+    st0, bk0 = ens.read_state(), ens.read_books()
+    ens.step(0)
+    _assert_books(descs, ens.read_books(), bk0)
+    _assert_states(ens.read_state(), st0)
+    ens.step(30)
+    ens.step(0)
+    ens.step(20)
+    rst, rbk = O.run(descs, 21, 50)
+    _assert_books(descs, ens.read_books(), rbk)
+    _assert_states(ens.read_state(), rst)
+    ens.close()
+
+
 def test_overflow_guard_refuses_launch():
     E = _engine()
     from paper_2606_21784_amd import _lib
