@@ -295,8 +295,8 @@ def dynamics_leg():
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-markets", type=int, default=1024)
     ap.add_argument("--no-uneven", action="store_true",
@@ -340,8 +340,11 @@ def main():
              "autotune_s": tune_s}
     log("schedule:", json.dumps(sched))
 
-    for _ in range(args.warmup):
+    first_bk = None  # books after the first launch, checked against the oracle below
+    for i in range(args.warmup):
         ens.step(S)
+        if i == 0:
+            first_bk = ens.read_books()
     torch.cuda.synchronize()
     snap_st, snap_bk = ens.read_state(), ens.read_books()
     guard = (2**32 - 1) // (A * int(d["Q"][0]))
@@ -411,8 +414,8 @@ def main():
         result["cpu_baseline"] = cb
         # the benchmarked kernel is the correct one: its first call matches the oracle
         n = args.cpu_markets
-        if args.warmup >= 1:
-            ok = np.array_equal(snap_bk[:n * 2 * L], rbk) if args.warmup == 1 else None
+        if first_bk is not None:
+            ok = np.array_equal(first_bk[:n * 2 * L], rbk)
             result["cpu_baseline"]["gpu_matches_oracle"] = ok
     ens.close()
     if not args.no_ablation:
