@@ -150,8 +150,12 @@ def tune(descs, seed=0, S_probe=None, min_markets=None, cache=None, arch="gfx950
                     run(w, False, G, share + 1)
         fastest = min(x[4] for x in timings)
         # fewest waves per market among the near-fastest (plain candidates come first, in
-        # increasing order of waves per market)
-        best = next(x for x in timings if x[4] <= fastest * (1.0 + TIE))
+        # increasing order of waves per market).  The overlapped candidates are one family,
+        # represented by its fastest member: the tie margin prefers a narrower schedule, not
+        # the first of several clearing shares that differ by noise.
+        ovl = [x for x in timings if x[3]]
+        family = [x for x in timings if not x[3]] + ([min(ovl, key=lambda x: x[4])] if ovl else [])
+        best = next(x for x in family if x[4] <= fastest * (1.0 + TIE))
         wpm[c] = best[0]
         pipe_c[c] = best[1]
         ovl_c[c] = best[3]
