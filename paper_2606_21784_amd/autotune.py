@@ -100,6 +100,7 @@ def tune(descs, seed=0, S_probe=None, min_markets=None, cache=None, arch="gfx950
     wpm = {}
     pipe_c = {}
     ovl_c = {}
+    ovl_at_g = {}  # class -> {waves per group: fastest clearing share measured there}
     cost = {}
     t0 = time.perf_counter()
     for c in sorted(set(cls.tolist())):
@@ -159,23 +160,30 @@ def tune(descs, seed=0, S_probe=None, min_markets=None, cache=None, arch="gfx950
         wpm[c] = best[0]
         pipe_c[c] = best[1]
         ovl_c[c] = best[3]
+        if best[3]:
+            ovl_at_g[c] = {G: min((x for x in ovl if x[2] == G), key=lambda x: x[4])[3]
+                           for G in sorted({x[2] for x in ovl})}
         # per market-step cost when the class fills the GPU alone
         cost[c] = best[4] * 1e6 / (len(probe) * Sp) * ncu
         cached[key] = {"waves_per_market": wpm[c], "pipelined": bool(pipe_c[c]), "overlap": ovl_c[c],
                        "ns_per_market_step": cost[c]}
     # waves per workgroup on the whole ensemble; classes that asked for more waves per market
     # than a candidate group holds are clamped to it
+    # (an overlapped class runs, at each candidate, the clearing share that was fastest at
+    # that workgroup size in its own probe, if it was probed there)
     best_g = None
     for G in GROUP_CANDIDATES:
+        ovl_g = {c: ovl_at_g.get(c, {}).get(G, k) for c, k in ovl_c.items() if k}
         tn = {"waves_per_group": G, "waves_per_market": {int(c): min(w, G) for c, w in wpm.items()},
               "pipelined": {int(c): 1 for c, p in pipe_c.items() if p},
-              "overlap": {int(c): k for c, k in ovl_c.items() if k}}
+              "overlap": {int(c): k for c, k in ovl_g.items()}}
         ms = _time_launch(descs, seed, tn, S_probe or probe_steps(descs))
         if log:
             log("waves_per_group %2d: %.3f ms" % (G, ms))
         if best_g is None or ms < best_g[1]:
-            best_g = (G, ms)
+            best_g = (G, ms, ovl_g)
     wpm = {c: min(w, best_g[0]) for c, w in wpm.items()}
+    ovl_c.update(best_g[2])
     if cache:
         allc = {}
         if os.path.exists(cache):
