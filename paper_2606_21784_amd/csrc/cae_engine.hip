@@ -9,8 +9,8 @@
 //   * A market is owned by a group of `wpm` wave64s (1..16).  All of them generate orders
 //     (agents strided over the group's lanes) and add them to the book in LDS with ds_add_u32.
 //     ONE wave then clears the whole book: each lane owns TPL contiguous ticks, in-lane serial
-//     sums plus a wave64 DPP scan give D and S, a DPP max plus a ballot gives the lowest tick of
-//     maximal volume, and the fill uses the closed form
+//     sums plus a wave64 DPP scan give D and S, two ballots at the crossing of D and S give the
+//     maximal volume and its lowest tick (no max reduction), and the fill uses the closed form
 //        fill_bid(q) = min(D(q), V*) - min(D(q+1), V*),  fill_ask(q) = min(S(q), V*) - min(S(q-1), V*).
 //     No cross-wave scan pass and only two barriers per step; the clearing wave rotates with the
 //     step so the clearing work spreads over the CU's four SIMDs.  Optionally (last-tick model)
