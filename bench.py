@@ -302,7 +302,7 @@ def main():
     ap.add_argument("--no-uneven", action="store_true",
                     help="skip the uneven-ensemble leg (batched launch vs per-size launches)")
     ap.add_argument("--no-surrogate", action="store_true",
-                    help="skip the calibration-surrogate leg (65536-draw sweep, training, judging)")
+                    help="skip the calibration-surrogate leg (65536-draw sweep, training, scoring)")
     ap.add_argument("--no-sweeps", action="store_true",
                     help="skip the sweep leg (paper shapes, step latency, market-count sweep)")
     ap.add_argument("--no-ablation", action="store_true",
