@@ -1156,6 +1156,12 @@ __device__ __forceinline__ void run_market_ovl(const EngineArgs &args, const Ite
             }
             __builtin_amdgcn_s_setprio(0);
         } else if (active && more) {
+            // Generating waves alternate between issue priorities 0 and 1 every block of steps,
+            // out of step between workgroups of even and odd index: the SIMD arbiter otherwise
+            // favours the oldest waves for the whole persistent launch, and the markets of the
+            // youngest workgroups on a CU set the launch's length.
+            if (((i >> kOvlBlockLog2) + blockIdx.x) & 1u) __builtin_amdgcn_s_setprio(1);
+            else __builtin_amdgcn_s_setprio(0);
             const uint32_t r = (w_in - c - 1u) & wpm_mask;  // 0 .. wpm - 2
             gen_rel(d, s + 1u, PhiloxStep(s + 1u, d.id, args.k0, args.k1), own + (r << 6), ostride, d.A, lane,
                     Hn);
