@@ -1334,6 +1334,9 @@ __device__ __forceinline__ void run_market_ovl_any(const EngineArgs &args, const
             }
             __builtin_amdgcn_s_setprio(0);
         } else if (active && more) {
+            // issue priority alternating by block and workgroup parity, as in run_market_ovl
+            if (((i >> kOvlBlockLog2) + blockIdx.x) & 1u) __builtin_amdgcn_s_setprio(1);
+            else __builtin_amdgcn_s_setprio(0);
             const uint32_t r = (w_in - c - 1u) & wpm_mask;  // 0 .. wpm - 2
             gen_bins(s + 1u, own + (r << 6), ostride, d.A, Hn);
         }
