@@ -7,9 +7,12 @@ One benchmark step = one cae_step call of S = 1000 steps over the fixed standard
 allocation, statistics, persistent loop) inside one launch.  Inputs are resident on the GPU
 before timing starts.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--copy-calib]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--verbose] [--detail PATH]
 
-Prints ONE JSON line on stdout (diagnostics go to stderr).
+Prints ONE compact JSON line on stdout, last: the headline, its roofline (VALU issue and LDS
+atomics), the oracle's CPU baseline and one short summary per leg.  Every leg's full detail goes
+to a JSON file (--detail, default gpurun_out/bench_detail.json); diagnostics go to stderr, the
+autotuner's per-candidate timings only with --verbose.
 """
 import argparse
 import hashlib
@@ -23,27 +26,56 @@ sys.path.insert(0, ROOT)
 
 METRIC = "agent events/s on 1 MI355X + roofline %; surrogate vs exact sweep speedup at ≤5% err"
 
-# --- roofline of the engine kernel (plain integer ALU work) --------------------------------
+# --- roofline of the engine kernel (plain integer VALU issue; LDS atomics second) -----------------
 # Peak: 256 CUs x 4 SIMDs x 16 lanes = 64 lane-slots per CU per clock at the 2.4 GHz peak
-# engine clock, for full-rate 32-bit VALU operations.
+# engine clock; a slot is one lane of one full-rate 32-bit VALU instruction.
 N_CU, LANES_PER_CU, CLOCK_HZ = 256, 64, 2.4e9
 PEAK_SLOTS = N_CU * LANES_PER_CU * CLOCK_HZ  # 3.93e13 slots/s
-# Issue cost in full-rate slots on gfx950, measured at saturation by
-# paper_2606_21784_amd/ubench.py (one workgroup of 16 waves per CU, wave64 instructions per clock
-# per CU): v_add/v_xor/v_bitop3 1.0, v_mul_hi_u32 1/0.824 = 1.21, v_mad_u64_u32 1/0.792 = 1.26.
-COST = {"mad_u64_u32": 1.26, "mul_hi_u32": 1.21, "alu": 1.0}
+# Issue costs in full-rate slots, measured on MI355X by paper_2606_21784_amd/ubench.py in the
+# form the engine issues each instruction (scalar multiplier, zero addend; inside Philox rounds),
+# at 16 waves per CU: the product v_mad_u64_u32 issues at the full rate in the generator's mix,
+# and so do the three-input xor (v_bitop3_b32) and v_mul_hi_u32 with a scalar operand.
+COST = {"mad_u64_u32": 1.0, "mul_hi_u32": 1.0, "alu": 1.0}
 # Algorithmic work per agent event, from the generator and order rules (not from compiled
 # code): Philox4x32-10 with counter (step, agent, market, 0) needs 16 agent-dependent
-# 32x32->64 products and 18 agent-dependent three-input xors; 2 multiply-high range
-# reductions; 5 ops to form the tick (add, clamp), the quantity and the book address.
-# Clearing costs 10 ops per tick per step, i.e. 10 L / A per event.
+# 32x32->64 products and 18 agent-dependent three-input xors (the agent word enters round 1
+# through an xor, so the products of rounds 1-3 that do not depend on it are computed once per
+# market-step: 4 of the 20 products per evaluation); 2 multiply-high range reductions (offset,
+# quantity); 5 ops to form the tick (add, clamp), the side and the book address.  Clearing costs
+# 10 ops per tick per step, i.e. 10 L / A per event.
 PHILOX_PRODUCTS, PHILOX_XORS, RANGE_MULHI, ORDER_OPS, CLEAR_OPS_PER_TICK = 16, 18, 2, 5, 10
+# LDS: one ds_add_u32 per event; the clearing wave reads and writes each tick's (bid, ask) pair
+# once per step (4 words), i.e. 4 L / A lane-words per event.  Sustained ds_add_u32 rate in the
+# engine's aggregation pattern (addresses in a 66-word window), lane-operations per CU per clock,
+# measured by ubench.py at 16 waves per CU.
+LDS_LANE_ATOMICS_PER_CLK_CU = 8.1
+LDS_WORDS_PER_TICK = 4
+PEAK_LDS = N_CU * LDS_LANE_ATOMICS_PER_CLK_CU * CLOCK_HZ
 
 
 def slots_per_event(L, A):
     return (PHILOX_PRODUCTS * COST["mad_u64_u32"] + PHILOX_XORS * COST["alu"]
             + RANGE_MULHI * COST["mul_hi_u32"] + ORDER_OPS * COST["alu"]
             + CLEAR_OPS_PER_TICK * COST["alu"] * L / A)
+
+
+def lds_ops_per_event(L, A):
+    return 1.0 + LDS_WORDS_PER_TICK * L / A
+
+
+def ceiling_events_per_s(L, A):
+    """R = min(P_v / w_v, P_l / w_l) for a market of L ticks and A agents."""
+    return min(PEAK_SLOTS / slots_per_event(L, A), PEAK_LDS / lds_ops_per_event(L, A))
+
+
+def ensemble_ceiling(descs):
+    """Ceiling of a whole ensemble: the time each market's events need at its own ceiling,
+    summed (work of different shapes adds up on one chip)."""
+    import numpy as np
+    A = descs["A"].astype(np.float64)
+    L = descs["L"].astype(np.float64)
+    t = sum(a / ceiling_events_per_s(l, a) for l, a in zip(L.tolist(), A.tolist()))
+    return float(A.sum()) / t
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "engine_fixed_M1024_L256_A1024_S1000.traffic.txt")
@@ -77,19 +109,45 @@ def measured_traffic():
         return None
 
 
-def cpu_baseline(w, n_markets):
+def cpu_threads():
+    """Threads for the multi-threaded oracle: the host's CPUs available to this process, at most
+    16 (one GPU's share of the host).  Returns (threads, nproc)."""
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except AttributeError:
+        nproc = os.cpu_count() or 1
+    return max(1, min(nproc, 16)), nproc
+
+
+def cpu_baseline(w, n_markets, n_markets_1t):
+    """The oracle (plain sequential C, one market at a time per thread) on the host cores: one
+    thread on the first n_markets_1t markets, then `cpu_threads()` threads on the first n_markets
+    markets (all steps).  Returns (record, states, books) of the multi-threaded run."""
     import numpy as np
 
     import oracle
-    descs = w["descs"][:n_markets]
-    nthreads = min(os.cpu_count() or 1, 16)
-    t0 = time.perf_counter()
-    st, bk = oracle.run(descs, w["seed"], w["S"], nthreads=nthreads)
-    dt = time.perf_counter() - t0
-    ev = float(np.sum(descs["A"].astype(np.float64))) * w["S"]
-    return {"value": ev / dt, "unit": "agent-events/s", "cores": nthreads, "kind": "oracle",
-            "sample": "%d of %d markets of %s, all %d steps (%.3g events, %.1f s wall)" %
-                      (n_markets, len(w["descs"]), w["name"], w["S"], ev, dt)}, st, bk
+    nthreads, nproc = cpu_threads()
+    rows = {}
+    for key, n, th in (("one_thread", n_markets_1t, 1), ("threads", n_markets, nthreads)):
+        descs = w["descs"][:n]
+        t0 = time.perf_counter()
+        st, bk = oracle.run(descs, w["seed"], w["S"], nthreads=th)
+        dt = time.perf_counter() - t0
+        ev = float(np.sum(descs["A"].astype(np.float64))) * w["S"]
+        rows[key] = {"events_per_s": ev / dt, "ns_per_event": 1e9 * dt / ev, "threads": th,
+                     "markets": n, "events": ev, "wall_s": dt}
+    mt = rows["threads"]
+    rec = {"value": mt["events_per_s"], "unit": "agent-events/s", "cores": nthreads, "kind": "oracle",
+           "ns_per_event": mt["ns_per_event"], "nproc": nproc,
+           "one_thread": {"value": rows["one_thread"]["events_per_s"],
+                          "ns_per_event": rows["one_thread"]["ns_per_event"],
+                          "markets": rows["one_thread"]["markets"]},
+           "sample": "%s, all %d steps: %d of %d markets on %d threads (%.3g events, %.1f s); "
+                     "%d markets on 1 thread (%.3g events, %.1f s)" %
+                     (w["name"], w["S"], n, len(w["descs"]), nthreads, mt["events"], mt["wall_s"],
+                      rows["one_thread"]["markets"], rows["one_thread"]["events"],
+                      rows["one_thread"]["wall_s"])}
+    return rec, st, bk
 
 
 def uneven_leg(reps=2):
@@ -121,7 +179,7 @@ def uneven_leg(reps=2):
         return best
 
     t0 = time.perf_counter()
-    tn = autotune.tune(d, seed=w["seed"], log=log)
+    tn = autotune.tune(d, seed=w["seed"], log=log if VERBOSE else None)
     tune_s = time.perf_counter() - t0
     ens = engine.Ensemble(d, w["seed"], tuning=tn)
     t_batched = timed([ens], reps)
@@ -149,6 +207,7 @@ def uneven_leg(reps=2):
            "untuned_batched_ms": 1e3 * t_default,
            "per_size_launches": len(groups), "per_size_ms": 1e3 * t_split,
            "per_size_events_per_s": events / t_split, "speedup_vs_per_size": t_split / t_batched,
+           "ceiling_frac": events / t_batched / ensemble_ceiling(d),
            "schedule": {"waves_per_group": sched["waves_per_group"],
                         "groups_per_cu": sched["groups_per_cu"],
                         "waves_per_market": {str(k): v for k, v in sched["waves_per_market"].items()},
@@ -219,10 +278,12 @@ def tuned_time(w, reps=2):
     used = ens.tuning()
     ens.close()
     ms = min(times)
+    frac = events / (ms * 1e-3) / ensemble_ceiling(d)
     sched = {"waves_per_group": used["waves_per_group"],
              "waves_per_market": sorted(set(used["waves_per_market"].values())),
              "pipelined": bool(used["pipelined"]),
              "overlap": sorted(set(used["overlap"].values()))}
+    sched["ceiling_frac"] = frac
     return ms, events / (ms * 1e-3), sched, times
 
 
@@ -292,13 +353,68 @@ def dynamics_leg():
     return out
 
 
+def leg_summaries(detail):
+    """One short record per leg for the result line (the full detail goes to the detail file)."""
+    out = {}
+    r = lambda x, n=4: float("%.*g" % (n, x))
+    if "ablation" in detail:
+        a = detail["ablation"]
+        out["ablation_naive_vs_persistent"] = {k: r(v["speedup"], 3) for k, v in a.items()}
+    if "sweeps" in detail:
+        sw = detail["sweeps"]
+        ms = sw["market_sweep"]
+        out["market_sweep_L512_A4096_S10000"] = {
+            "M": [int(k) for k in ms], "events_per_s": [r(v["events_per_s"], 3) for v in ms.values()],
+            "ceiling_frac": [r(v["schedule"]["ceiling_frac"], 3) for v in ms.values()]}
+        pm = sw["paper_market_sweep"]
+        out["paper_market_sweep_A256_L128_S500"] = {
+            "M": [int(k) for k in pm], "events_per_s": [r(v["events_per_s"], 3) for v in pm.values()]}
+        pa = sw["paper_agent_sweep"]
+        out["paper_agent_sweep_M8192_L128_S500"] = {
+            "A": [int(k) for k in pa], "events_per_s": [r(v["events_per_s"], 3) for v in pa.values()],
+            "ceiling_frac": [r(v["schedule"]["ceiling_frac"], 3) for v in pa.values()]}
+        pf = sw["paper_fixed"]
+        out["paper_fixed_M8192_A256_L128_S500"] = {"ms": r(pf["ms"]), "events_per_s": r(pf["events_per_s"], 3)}
+        out["step_latency_M4096_A256_us"] = r(sw["step_latency"]["median_us"], 3)
+    if "dynamics" in detail:
+        dy = detail["dynamics"]
+        out["dynamics_M3840_L128_S1000"] = {k: {"kernel_ms": r(v["timing"]["kernel_ms"]),
+                                                "events_per_s": r(v["timing"]["events_per_s"], 3)}
+                                            for k, v in dy.items() if isinstance(v, dict)}
+    if "uneven" in detail:
+        u = detail["uneven"]
+        out["uneven_M8192_S2000"] = {"batched_ms": r(u["batched_ms"]), "per_size_ms": r(u["per_size_ms"]),
+                                     "per_size_launches": u["per_size_launches"],
+                                     "speedup": r(u["speedup_vs_per_size"], 3),
+                                     "events_per_s": r(u["batched_events_per_s"], 3),
+                                     "ceiling_frac": r(u["ceiling_frac"], 3)}
+    if "surrogate" in detail:
+        sg = detail["surrogate"]
+        names = ("mean_spread", "logret_variance", "mean_volume")
+        out["surrogate_65536_draws"] = {
+            "speedup": r(sg["speedup"], 4), "exact_s": r(sg["exact_test_sweep_s"]),
+            "surrogate_s": r(sg["surrogate_test_sweep_s"], 3),
+            "mean_rel_err": [r(sg["surrogate_rel_err"][k]["mean"], 3) for k in names],
+            "p95_rel_err": [r(sg["surrogate_rel_err"][k]["p95"], 3) for k in names],
+            "noise_floor_mean": [r(sg["mc_noise_rel_diff"][k]["mean"], 3) for k in names],
+            "linear_mean_rel_err": [r(sg["linear_predictor_rel_err"][k]["mean"], 3) for k in names]}
+    return out
+
+
+VERBOSE = False
+
+
 def main():
+    global VERBOSE
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--cpu-markets", type=int, default=1024)
+    ap.add_argument("--cpu-markets", type=int, default=1024,
+                    help="markets of the fixed workload the multi-threaded oracle runs")
+    ap.add_argument("--cpu-markets-1t", type=int, default=32,
+                    help="markets of the fixed workload the one-thread oracle runs")
     ap.add_argument("--no-uneven", action="store_true",
                     help="skip the uneven-ensemble leg (batched launch vs per-size launches)")
     ap.add_argument("--no-surrogate", action="store_true",
@@ -309,9 +425,14 @@ def main():
                     help="skip the naive-engine ablation leg")
     ap.add_argument("--no-dynamics", action="store_true",
                     help="skip the agent-mix dynamics leg (traced sweep, stylized facts)")
+    ap.add_argument("--verbose", action="store_true",
+                    help="log the autotuner's per-candidate timings and training progress")
+    ap.add_argument("--detail", default=os.path.join(ROOT, "gpurun_out", "bench_detail.json"),
+                    help="file for every leg's full detail (JSON)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="after timing, copy 1 GiB device-to-device (counter calibration)")
     args = ap.parse_args()
+    VERBOSE = args.verbose
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this engine has no multi-GPU path (markets would be "
               "sharded with no communication); run with --gpus 1", file=sys.stderr)
@@ -330,14 +451,14 @@ def main():
     events = float(np.sum(d["A"].astype(np.float64))) * S
     from paper_2606_21784_amd import autotune
     t0 = time.perf_counter()
-    tn = autotune.tune(d, seed=w["seed"])
+    tn = autotune.tune(d, seed=w["seed"], log=log if VERBOSE else None)
     tune_s = time.perf_counter() - t0
     ens = engine.Ensemble(d, w["seed"], tuning=tn)
     sched = ens.tuning()
     sched = {"waves_per_group": sched["waves_per_group"], "groups_per_cu": sched["groups_per_cu"],
              "waves_per_market": sorted(set(sched["waves_per_market"].values())),
              "pipelined": bool(sched["pipelined"]), "overlap": sorted(set(sched["overlap"].values())),
-             "autotune_s": tune_s}
+             "autotune_s": round(tune_s, 2)}
     log("schedule:", json.dumps(sched))
 
     first_bk = None  # books after the first launch, checked against the oracle below
@@ -389,14 +510,18 @@ def main():
         log("copy calibration: 1 GiB read + 1 GiB written")
 
     w_ev = slots_per_event(L, A)
-    achieved = events * w_ev / (kms * 1e-3)
-    traffic = measured_traffic()
+    w_lds = lds_ops_per_event(L, A)
+    rate = events / (kms * 1e-3)  # kernel-time events/s
+    achieved = rate * w_ev
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12,
-            "unit": "Tslot/s", "frac": achieved / PEAK_SLOTS, "traffic": traffic,
-            "kernel": "cae_engine_kernel<%d, false, false>" % max(1, L // 64), "kernel_ms": kms,
-            "kernel_ms_last_launch": min(last_ms),
-            "slots_per_event": w_ev, "events_per_launch": events,
-            "roofline_events_per_s": PEAK_SLOTS / w_ev}
+            "unit": "TOP/s", "frac": achieved / PEAK_SLOTS, "traffic": measured_traffic(),
+            "kernel": "cae_engine_kernel<%d,false,false>" % max(1, L // 64), "kernel_ms": kms,
+            "kernel_ms_last_launch": min(last_ms), "ops_per_event": w_ev,
+            "lds": {"achieved": rate * w_lds / 1e12, "peak": PEAK_LDS / 1e12,
+                    "unit": "T lane-atomics/s", "frac": rate * w_lds / PEAK_LDS,
+                    "ops_per_event": w_lds},
+            "ceiling_events_per_s": ceiling_events_per_s(L, A),
+            "ceiling_frac": rate / ceiling_events_per_s(L, A)}
 
     result = {
         "metric": METRIC, "value": value, "unit": "agent-events/s", "n_gpus": 1,
@@ -410,29 +535,42 @@ def main():
         "roofline": roof,
     }
     if not args.no_cpu:
-        cb, rst, rbk = cpu_baseline(w, args.cpu_markets)
-        result["cpu_baseline"] = cb
+        cb, rst, rbk = cpu_baseline(w, args.cpu_markets, args.cpu_markets_1t)
         # the benchmarked kernel is the correct one: its first call matches the oracle
         n = args.cpu_markets
         if first_bk is not None:
-            ok = np.array_equal(first_bk[:n * 2 * L], rbk)
-            result["cpu_baseline"]["gpu_matches_oracle"] = ok
+            cb["gpu_matches_oracle"] = bool(np.array_equal(first_bk[:n * 2 * L], rbk))
+        result["cpu_baseline"] = cb
+        log("cpu baseline: %.3g events/s on %d threads (%.1f ns/event), %.3g on 1 thread" %
+            (cb["value"], cb["cores"], cb["ns_per_event"], cb["one_thread"]["value"]))
     ens.close()
+    detail = {}
     if not args.no_ablation:
-        result["ablation"] = ablation_leg()
+        detail["ablation"] = ablation_leg()
     if not args.no_sweeps:
-        result["sweeps"] = sweeps_leg()
+        detail["sweeps"] = sweeps_leg()
     if not args.no_dynamics:
-        result["dynamics"] = dynamics_leg()
+        detail["dynamics"] = dynamics_leg()
     if not args.no_uneven:
-        result["uneven"] = uneven_leg()
+        detail["uneven"] = uneven_leg()
     if not args.no_surrogate:
         from paper_2606_21784_amd import surrogate
-        rep, _, _ = surrogate.run(log=log)
-        result["surrogate"] = rep
+        rep, _, _ = surrogate.run(log=log if VERBOSE else None)
+        detail["surrogate"] = rep
         log("surrogate: speedup %.0f, mean rel err %s" %
             (rep["speedup"], {k: round(v["mean"], 4) for k, v in rep["surrogate_rel_err"].items()}))
-    print(json.dumps(result), flush=True)
+    result["legs"] = leg_summaries(detail)
+    result["detail_file"] = os.path.relpath(args.detail, ROOT)
+    try:
+        os.makedirs(os.path.dirname(os.path.abspath(args.detail)), exist_ok=True)
+        with open(args.detail, "w") as f:
+            json.dump(dict(result, detail=detail), f, indent=1)
+    except OSError as e:
+        log("could not write %s: %s" % (args.detail, e))
+    line = json.dumps(result, separators=(",", ":"))
+    print(line, flush=True)
+    if len(line) > 4096:
+        log("warning: the result line is %d characters" % len(line))
 
 
 if __name__ == "__main__":

@@ -175,14 +175,17 @@ const char *cae_last_error(void);
  * library version.  Either pointer may be NULL. */
 int cae_device_info(uint32_t *num_cu, uint32_t *version);
 
-/* Sizes of the device buffers for M markets described by host array desc[M].  Pure host
- * computation.  CAE_EINVAL on a bad descriptor (the message names the market). */
+/* Sizes of the device buffers for M markets described by host array desc[M] (the inputs of
+ * Algorithm 1, "REQUIRE": M markets, each with its A agents and L price ticks; the books of
+ * section III-B, here bid[L] and ask[L] per market).  Pure host computation; nothing is
+ * allocated.  CAE_EINVAL on a bad descriptor (the message names the market). */
 int cae_sizes(const cae_market *desc, uint32_t M, cae_sizes_t *out);
 
 /* Create an ensemble of M markets (Algorithm 1, "REQUIRE": M markets with their A agents
- * and L ticks; section III-B: books start empty at the opening price).  Copies the
- * descriptors and schedule into dev->workspace, zeroes dev->book and writes the opening
- * state to dev->state, ordered on `stream`; returns after those copies completed.
+ * and L ticks).  The paper seeds opening quotes (Algorithm 1, section III-B) without stating
+ * them; this library's reading is an empty opening book with last = prev = floor(L / 2).
+ * Copies the descriptors and schedule into dev->workspace, zeroes dev->book and writes the
+ * opening state to dev->state, ordered on `stream`; returns after those copies completed.
  * market_ids (host, M entries, may be NULL = 0..M-1) is the market index each market uses in
  * the generator counter, so a subset of a larger ensemble (a shard, or one size group)
  * reproduces that ensemble's markets bit for bit.  tuning may be NULL (automatic schedule).
@@ -213,16 +216,24 @@ int cae_step_traced(cae_ensemble *e, uint32_t S, uint32_t *dev_price, uint32_t *
                     uint64_t ld);
 
 /* Copy the packed books (layout of cae_buffers.book) to host_book[n_words] after the
- * stream's pending work; returns when the copy is complete.  CAE_ENOSPACE if n_words is
- * smaller than book_words. */
+ * stream's pending work; returns when the copy is complete.  These are the final books that
+ * Algorithm 1 leaves in global memory ("ENSURE": the final limit-order books).
+ * CAE_ENOSPACE if n_words is smaller than book_words; CAE_EINVAL on NULL; CAE_EHIP. */
 int cae_read_books(cae_ensemble *e, uint32_t *host_book, uint64_t n_words);
 
-/* Copy the M states to host_state[M]; synchronous like cae_read_books. */
+/* Copy the M states (price, step counter and clearing statistics: Algorithm 1, "ENSURE": the
+ * clearing statistics in global memory) to host_state[M]; synchronous like cae_read_books.
+ * CAE_ENOSPACE if M is smaller than the ensemble's; CAE_EINVAL on NULL; CAE_EHIP. */
 int cae_read_state(cae_ensemble *e, cae_state *host_state, uint32_t M);
 
-/* Replace the device books and states with host copies (checkpoint resume).  host_book
- * must hold book_words words in the packed layout.  CAE_EINVAL if M or n_words do not
- * match the ensemble or a state is inconsistent with its market (last or prev >= L). */
+/* Replace the device books and states with host copies (checkpoint resume: the books and
+ * statistics one call leaves, Algorithm 1 "ENSURE", become the starting state of the next
+ * call).  host_book must hold book_words words in the packed layout.  Synchronous.
+ * CAE_EINVAL, writing nothing, if M or n_words do not match the ensemble, or a state is
+ * inconsistent with its market: last or prev >= L, ref2 > 2 (L - 1), reserved != 0,
+ * steps_done A Q >= 2^32, or a book holding more than steps_done A Q shares on its two sides
+ * together (more than steps_done steps can add; cae_step's overflow guard relies on that
+ * bound).  CAE_EHIP. */
 int cae_write_state(cae_ensemble *e, const cae_state *host_state, uint32_t M,
                     const uint32_t *host_book, uint64_t n_words);
 
@@ -240,7 +251,9 @@ int cae_step_naive(cae_ensemble *e, uint32_t S);
  * recorded on the ensemble's stream around the kernel; waits for that launch to finish. */
 int cae_last_step_ms(cae_ensemble *e, float *ms);
 
-/* Release the host handle.  Device buffers stay owned by the caller. */
+/* Release the host handle made by cae_create (host metadata only).  The device buffers, which
+ * hold the ensemble's books and statistics (Algorithm 1, "ENSURE"), stay owned by the caller
+ * and keep their contents.  NULL is accepted.  Always CAE_OK. */
 int cae_destroy(cae_ensemble *e);
 
 /* One clearing pass over M books of L ticks each (Eq. 1, Eq. 2 and price-priority fill;

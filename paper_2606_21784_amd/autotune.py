@@ -141,14 +141,13 @@ def tune(descs, seed=0, S_probe=None, min_markets=None, cache=None, arch="gfx950
         # overlapped lock-step at the fastest plain lock-step width, one or two markets per
         # workgroup: the clearing wave takes from none to all of an even share of the market's
         # rows of 64 agents (at most 5 steps)
-        if overlap_possible(descs):
-            lock = min((x for x in timings if x[0] >= 2 and not x[1]), key=lambda x: x[4])
-            w = lock[0]
-            rows = -(-int(probe["A"].max()) // 64)
-            even = rows // w
-            for G in sorted({max(4, w), min(16, 2 * max(4, w))}):
-                for share in sorted({min(even, (even * j + 3) // 4) for j in range(5)}):
-                    run(w, False, G, share + 1)
+        lock = min((x for x in timings if x[0] >= 2 and not x[1]), key=lambda x: x[4])
+        w = lock[0]
+        rows = -(-int(probe["A"].max()) // 64)
+        even = rows // w
+        for G in sorted({max(4, w), min(16, 2 * max(4, w))}):
+            for share in sorted({min(even, (even * j + 3) // 4) for j in range(5)}):
+                run(w, False, G, share + 1)
         fastest = min(x[4] for x in timings)
         # fewest waves per market among the near-fastest (plain candidates come first, in
         # increasing order of waves per market).  The overlapped candidates are one family,
@@ -200,12 +199,6 @@ def tune(descs, seed=0, S_probe=None, min_markets=None, cache=None, arch="gfx950
               "class_cost_ns": {int(c): float(v) for c, v in cost.items()},
               "tune_seconds": time.perf_counter() - t0}
     return result
-
-
-def overlap_possible(descs):
-    """Whether the engine can run an overlapped schedule for these markets (every agent model
-    and generator can)."""
-    return len(descs) > 0
 
 
 def per_size_groups(descs):

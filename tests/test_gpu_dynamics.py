@@ -27,5 +27,34 @@ def test_sweep_series_and_stats_match_oracle():
             want = v[j * len(alphas):(j + 1) * len(alphas)].numpy()
             np.testing.assert_allclose(got, want, rtol=1e-9, atol=1e-12, err_msg="%d %s" % (A, k))
     assert timing["events"] == float(d["A"].astype(np.float64).sum()) * S
-    f = dynamics.facts(report, A=256, standard_alpha=0.15)
-    assert isinstance(f["volatility_increases"], bool)
+
+
+@pytest.mark.parametrize("model", ["last_tick", "mid_price"])
+def test_reproduced_facts_autotuned(model):
+    """1000-step sweep at A = 256 in the autotuned schedule: the statistics equal those of the
+    oracle's traces, and the facts the engine reproduces hold (volatility and volume rise with
+    alpha_mom; in the mid-price model returns reverse at lag 1 at alpha_mom = 0.15).  Fat tails
+    and volatility clustering are reported by the benchmark, not asserted."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2606_21784_amd._lib import MODEL_MID
+    from paper_2606_21784_amd.engine import model_flags
+    flags = model_flags(MODEL_MID, 0.05) if model == "mid_price" else 0
+    alphas, markets, S = (0.0, 0.15, 0.7), 8, 1000
+    report, _ = dynamics.run_sweep(A_values=(256,), alphas=alphas, markets=markets, S=S, flags=flags,
+                                   tuning="auto")
+    d = dynamics.composition_descs(256, markets=markets, alphas=alphas, flags=flags)
+    st, bk, pr, vo = O.run(d, 6, S, trace=True)
+    ref = dynamics.series_stats(torch.from_numpy(pr.astype(np.int64)),
+                                torch.from_numpy(vo.astype(np.int64)), 128,
+                                torch.full((len(d),), 64), groups=len(alphas))
+    for k, v in ref.items():
+        np.testing.assert_allclose(np.array(report[256][k], dtype=np.float64), v.numpy(), rtol=1e-9,
+                                   atol=1e-12, err_msg=k)
+    rep = {k: np.array(v, dtype=np.float64) for k, v in report[256].items()}
+    assert rep["tick_change_std"][-1] > (1.05 if flags else 1.2) * rep["tick_change_std"][0]
+    assert rep["price_std"][-1] > 2.0 * rep["price_std"][0]
+    assert rep["mean_volume"][-1] > 1.5 * rep["mean_volume"][0]
+    if flags:
+        assert rep["acf_r"][1][0] < -0.2

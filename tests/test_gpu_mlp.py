@@ -74,7 +74,12 @@ def test_predict_rejects_wide_hidden_layer():
     assert rc == _lib.CAE_EINVAL
 
 
-@pytest.mark.parametrize("dims,N", [((4, 256, 3), 256), ((7, 48, 5), 37)])
+# Batches above 256 samples split the weight gradients' batch dimension over workgroups (a
+# fixed-order sum of partial products): 257 (a one-sample second part), 1000 (ragged last part),
+# 1024 (the training batch, 4 parts), 4097 (17 parts).
+@pytest.mark.parametrize("dims,N", [((4, 256, 3), 256), ((7, 48, 5), 37), ((4, 256, 3), 257),
+                                    ((4, 256, 3), 1000), ((4, 256, 3), 1024), ((4, 256, 3), 4097),
+                                    ((7, 48, 5), 600)])
 def test_backward_matches_oracle(dims, N):
     import torch
     M = _mlp()

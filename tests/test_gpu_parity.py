@@ -179,6 +179,20 @@ def test_write_state_rejects_bad_input():
         ens.write_state(st[:1], bk)
     with pytest.raises(_lib.CaeError):
         ens.write_state(st, bk[:-1])
+    # a book holding more shares than steps_done steps can have added (the overflow guard's
+    # premise): at 0 steps any share is too many; after 3 steps at most 3 A Q = 240 per market
+    fat = bk.copy()
+    fat[5] = 1
+    with pytest.raises(_lib.CaeError, match="shares"):
+        ens.write_state(st, fat)
+    st3 = st.copy()
+    st3["steps_done"] = 3
+    ok = bk.copy()
+    ok[0], ok[64 + 1] = 120, 120  # market 0: 240 shares over its two sides
+    ens.write_state(st3, ok)
+    ok[2 * 64 + 7] = 241  # market 1: one share too many on one side
+    with pytest.raises(_lib.CaeError, match="market 1"):
+        ens.write_state(st3, ok)
     ens.close()
 
 
@@ -312,7 +326,6 @@ def test_fixed_workload_full_parity(schedule, fixed_reference):
     _assert_states(st, rst)
 
 
-@pytest.mark.slow
 def _tuned(descs, seed):
     _engine()
     from paper_2606_21784_amd import autotune
@@ -332,6 +345,33 @@ def test_market_sweep_sampled(schedule):
         rst, rbk = O.run(w["descs"][ids], w["seed"], w["S"], ids=ids)
         _assert_books(w["descs"], bk, rbk, ids=ids)
         _assert_states(st[ids], rst)
+
+
+@pytest.mark.parametrize("M", [4096, 65536])
+def test_market_sweep_large_sampled(M):
+    """Market-count sweep at large M in the schedule the benchmark times there (the autotuner's,
+    chosen for this M), full 10000 steps; four markets (first, a third, the middle, last)
+    re-simulated alone by the oracle and compared bit for bit, and every market's statistics
+    checked for the invariants that hold at any size."""
+    w = W.market_sweep(M)
+    tn = _tuned(w["descs"], w["seed"])
+    st, bk, used = _run_gpu(w["descs"], w["seed"], [w["S"]], tuning=tn)
+    assert used["waves_per_group"] == tn["waves_per_group"]
+    ids = [0, M // 3, M // 2, M - 1]
+    rst, rbk = O.run(w["descs"][ids], w["seed"], w["S"], ids=ids)
+    _assert_books(w["descs"], bk, rbk, ids=ids)
+    _assert_states(st[ids], rst)
+    L = int(w["descs"]["L"][0])
+    assert (st["steps_done"] == w["S"]).all()
+    assert (st["last"] < L).all() and (st["prev"] < L).all()
+    assert (st["n_trade"] <= w["S"]).all() and (st["n_spread"] <= w["S"]).all()
+    assert (st["sum_px"] <= st["n_trade"] * (L - 1)).all()
+    # residual books are never crossed: highest bid below lowest ask in every market
+    b = bk.reshape(M, 2, L)
+    has_b, has_a = (b[:, 0] > 0).any(1), (b[:, 1] > 0).any(1)
+    hb = np.where(has_b, L - 1 - np.argmax(b[:, 0, ::-1] > 0, axis=1), -1)
+    la = np.where(has_a, np.argmax(b[:, 1] > 0, axis=1), L)
+    assert (hb < la).all()
 
 
 @pytest.mark.slow

@@ -31,6 +31,22 @@ def test_exact_statistics_match_oracle():
         np.testing.assert_allclose(Y[k], ref, rtol=1e-9)
 
 
+def test_exact_statistics_sweep_schedule_full_steps():
+    """The calibration sweep's exact statistics as the sweep computes them: 64 markets per draw,
+    2000 steps, in the autotuner's schedule for the sweep (the one the timed held-out sweep
+    runs), three draws against the oracle's pooled statistics."""
+    SG = _sur()
+    tn = SG.sweep_tuning()
+    theta = W.calibration_params(100)[[9, 19, 58]]
+    ids = np.array([9, 19, 58])
+    Y = SG.exact_stats(theta, ids, tuning=tn)
+    S, mpd = W.CALIB_S, W.CALIB_MARKETS
+    for k in range(3):
+        d = W.calibration_markets(theta[k:k + 1], markets_per_draw=mpd)
+        st, _ = oracle.run(d, W.CALIB_SEED, S, ids=ids[k] * mpd + np.arange(mpd))
+        np.testing.assert_allclose(Y[k], oracle.pooled_stats(st, S), rtol=1e-9)
+
+
 def test_surrogate_beats_networkless_predictors():
     SG = _sur()
     data = SG.generate(n_draws=2048, markets_per_draw=16, S=400)
@@ -41,5 +57,7 @@ def test_surrogate_beats_networkless_predictors():
         assert s[name]["mean"] < 0.5 * lin[name]["mean"], (name, s[name], lin[name])
         assert s[name]["mean"] < 0.5 * mean[name]["mean"], (name, s[name], mean[name])
     assert rep["speedup"] > 10
+    print("surrogate", s, "linear", lin, "mean", mean, "speedup", rep["speedup"], flush=True)
     demo = SG.calibration_demo(net, scaler, data, n_targets=2, n_candidates=2048, verify=2)
+    print("calibration", demo, flush=True)
     assert np.isfinite(demo["surrogate_dist_mean"]) and np.isfinite(demo["exact_only_dist_mean"])
