@@ -282,7 +282,8 @@ def tuned_time(w, reps=2):
     sched = {"waves_per_group": used["waves_per_group"],
              "waves_per_market": sorted(set(used["waves_per_market"].values())),
              "pipelined": bool(used["pipelined"]),
-             "overlap": sorted(set(used["overlap"].values()))}
+             "overlap": sorted(set(used["overlap"].values())),
+             "pack": sorted(set(used["pack"].values()))}
     sched["ceiling_frac"] = frac
     return ms, events / (ms * 1e-3), sched, times
 

@@ -161,6 +161,15 @@ typedef struct cae_tuning {
     float class_cost[CAE_NUM_CLASSES];          /* relative cost of one market-step per
                                                    class for the longest-first order;
                                                    0 = the built-in model A + 2*64*TPL    */
+    uint8_t pack[CAE_NUM_CLASSES];              /* P = 2 or 4: P small markets of this class
+                                                   share one wave, 64/P lanes each, for the
+                                                   orders (rows of 64/P agents) and for the
+                                                   clearing (one book per lane segment);
+                                                   0 = off.  Applies to last-tick Philox
+                                                   markets with L <= 256/P (others of the
+                                                   class run unpacked); the class then runs
+                                                   one wave per P markets (waves_per_market,
+                                                   pipelined and overlap are ignored).     */
 } cae_tuning;
 
 typedef struct cae_ensemble cae_ensemble;
@@ -323,6 +332,22 @@ int cae_mlp_backward(const cae_mlp *net, const float *x, const float *dy, float 
  * copies.  Asynchronous. */
 int cae_mlp_adam(const cae_mlp *net, const float *grads, float *m, float *v, uint32_t step, float lr, float beta1,
                  float beta2, float eps, void *stream);
+
+/* One training step fused into two launches: forward pass on the batch, the mean loss over its
+ * N d_out outputs (kind and delta as in cae_mlp_loss_grad) and its gradient, back-propagation,
+ * and an Adam step (as cae_mlp_adam) that also refreshes the bfloat16 weight copies.  Same
+ * rounding points and fp32 accumulation as cae_mlp_forward + cae_mlp_loss_grad +
+ * cae_mlp_backward + cae_mlp_adam; each weight gradient is reduced over the whole batch by one
+ * wave in a fixed order (deterministic; the sums run in another order than the unfused path's).
+ * x[n][d_in] and target[n][d_out] (fp32, device) hold all samples; idx (device, N entries, may be
+ * NULL = rows 0..N-1) lists the rows of this batch.  m, v: Adam moments (device, n_params fp32).
+ * loss (device): receives the batch's mean loss.  grads (device, n_params fp32, may be NULL):
+ * receives the gradient.  ws: workspace of cae_mlp_sizes with max_batch >= N.
+ * Requires d_hidden a multiple of 32 up to 256 and d_in <= 32.  Asynchronous.
+ * Errors: CAE_EINVAL (shape, NULL, N == 0, step == 0, loss kind, delta), CAE_EHIP. */
+int cae_mlp_train_step(const cae_mlp *net, const float *x, const float *target, const uint32_t *idx, uint32_t N,
+                       float *m, float *v, uint32_t step, float lr, float beta1, float beta2, float eps, int loss_kind,
+                       float delta, float *loss, float *grads, void *ws, void *stream);
 
 /* Mean loss over n values and its gradient with respect to y, r = y - target (device pointers;
  * one workgroup, fixed summation order).  Asynchronous.

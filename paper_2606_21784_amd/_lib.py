@@ -48,7 +48,8 @@ class Tuning(C.Structure):
                 ("waves_per_market", C.c_uint8 * NUM_CLASSES),
                 ("pipelined", C.c_uint8 * NUM_CLASSES),
                 ("overlap", C.c_uint8 * NUM_CLASSES),
-                ("class_cost", C.c_float * NUM_CLASSES)]
+                ("class_cost", C.c_float * NUM_CLASSES),
+                ("pack", C.c_uint8 * NUM_CLASSES)]
 
 
 class Mlp(C.Structure):
@@ -70,8 +71,9 @@ class CaeError(RuntimeError):
 EXPORTS = ["cae_strerror", "cae_last_error", "cae_device_info", "cae_sizes", "cae_create",
            "cae_step", "cae_step_naive", "cae_step_traced", "cae_read_books", "cae_read_state", "cae_write_state", "cae_get_tuning",
            "cae_last_step_ms", "cae_destroy", "cae_clear", "cae_mlp_sizes",
-           "cae_mlp_refresh_weights", "cae_mlp_forward", "cae_mlp_predict", "cae_mlp_backward",
-           "cae_mlp_adam",
+           "cae_mlp_refresh_weights", "cae_mlp_forward", "cae_mlp_predict",
+           "cae_mlp_backward",
+           "cae_mlp_adam", "cae_mlp_train_step",
            "cae_mlp_loss_grad"]
 
 _lib = None
@@ -110,6 +112,7 @@ def lib():
     L.cae_mlp_backward.argtypes = [P, P, P, P, u32, P, P]
     L.cae_mlp_adam.argtypes = [P, P, P, P, u32, f32, f32, f32, f32, P]
     L.cae_mlp_loss_grad.argtypes = [P, P, P, P, u32, i32, f32, P]
+    L.cae_mlp_train_step.argtypes = [P, P, P, P, u32, P, P, u32, f32, f32, f32, f32, i32, f32, P, P, P, P]
     for name in EXPORTS:
         if name not in ("cae_strerror", "cae_last_error"):
             getattr(L, name).restype = i32

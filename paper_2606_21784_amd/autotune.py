@@ -8,6 +8,8 @@ The engine's schedule has these knobs (``cae_tuning`` in include/cae.h):
   * overlap, per size class (lock-step classes, either agent model): the market's other waves
     generate the next step's orders while one wave clears, the clearing wave taking overlap - 1
     rows of 64 agents after its clearing;
+  * pack, per size class (small last-tick markets in an ensemble of books of at most 128
+    ticks): P = 2 or 4 markets share one wave, 64 / P lanes each;
   * waves per workgroup: how many markets of one class share a workgroup (in lock-step when a
     market spans more than one wave) and therefore how the workgroup's LDS is partitioned into
     market slices;
@@ -27,6 +29,8 @@ from . import engine
 
 WPM_CANDIDATES = (1, 2, 4, 8, 16)
 PIPE_GROUPS = (4, 8)
+PACK_CANDIDATES = (2, 4)
+PACK_MAX_L = 128  # packing applies in ensembles whose books have at most this many ticks
 GROUP_CANDIDATES = (4, 8, 16)
 # A candidate within this fraction of the fastest counts as a tie; ties go to the schedule
 # with fewer waves per market, which leaves the whole ensemble more freedom of group size.
@@ -100,6 +104,8 @@ def tune(descs, seed=0, S_probe=None, min_markets=None, cache=None, arch="gfx950
     wpm = {}
     pipe_c = {}
     ovl_c = {}
+    pack_c = {}
+    small_books = int(descs["L"].max()) <= PACK_MAX_L
     ovl_at_g = {}  # class -> {waves per group: fastest clearing share measured there}
     cost = {}
     t0 = time.perf_counter()
@@ -109,6 +115,7 @@ def tune(descs, seed=0, S_probe=None, min_markets=None, cache=None, arch="gfx950
             wpm[c] = int(cached[key]["waves_per_market"])
             pipe_c[c] = bool(cached[key].get("pipelined", False))
             ovl_c[c] = int(cached[key].get("overlap", 0))
+            pack_c[c] = int(cached[key].get("pack", 0))
             cost[c] = float(cached[key]["ns_per_market_step"])
             continue
         idx = np.nonzero(cls == c)[0]
@@ -118,30 +125,37 @@ def tune(descs, seed=0, S_probe=None, min_markets=None, cache=None, arch="gfx950
         probe = _probe_set(descs, idx, n, rng)
         Sp = S_probe or probe_steps(probe)
         events = float(probe["A"].astype(np.float64).sum()) * Sp
-        cands = [(w, False, max(4, w), 0) for w in WPM_CANDIDATES] + [(1, True, G, 0) for G in PIPE_GROUPS]
+        # packed candidates first (the narrowest schedules): small last-tick Philox markets
+        packable = (small_books and int(probe["flags"].max()) == 0)
+        cands = [(1, False, G, 0, P) for P in PACK_CANDIDATES for G in (4, 8)
+                 if packable and int(probe["L"].max()) <= 256 // P]
+        cands += [(w, False, max(4, w), 0, 0) for w in WPM_CANDIDATES] + [(1, True, G, 0, 0) for G in PIPE_GROUPS]
         best = None
         timings = []
 
-        def run(w, pipe, G, k):
+        def run(w, pipe, G, k, P=0):
             tn = {"waves_per_group": G, "waves_per_market": {int(c): w}}
             if pipe:
                 tn["pipelined"] = {int(c): 1}
             if k:
                 tn["overlap"] = {int(c): k}
+            if P:
+                tn["pack"] = {int(c): P}
             ms = _time_launch(probe, seed, tn, Sp)
             if log:
-                mode = ("pipelined G=%d" % G) if pipe else "wpm %2d" % w + (" overlap %d" % k if k else "")
+                mode = ("pipelined G=%d" % G) if pipe else (("packed %d per wave G=%d" % (P, G)) if P else
+                                                            "wpm %2d" % w + (" overlap %d" % k if k else ""))
                 log("class %2d (L<=%4d, A~2^%d) %s: %.3f ms, %.3g events/s" %
                     (c, 64 << (c // 8), 6 + c % 8, mode, ms, events / (ms * 1e-3)))
-            timings.append((w, pipe, G, k, ms))
+            timings.append((w, pipe, G, k, ms, P))
             return ms
 
-        for w, pipe, G, k in cands:
-            run(w, pipe, G, k)
+        for w, pipe, G, k, P in cands:
+            run(w, pipe, G, k, P)
         # overlapped lock-step at the fastest plain lock-step width, one or two markets per
         # workgroup: the clearing wave takes from none to all of an even share of the market's
         # rows of 64 agents (at most 5 steps)
-        lock = min((x for x in timings if x[0] >= 2 and not x[1]), key=lambda x: x[4])
+        lock = min((x for x in timings if x[0] >= 2 and not x[1] and not x[5]), key=lambda x: x[4])
         w = lock[0]
         rows = -(-int(probe["A"].max()) // 64)
         even = rows // w
@@ -159,13 +173,14 @@ def tune(descs, seed=0, S_probe=None, min_markets=None, cache=None, arch="gfx950
         wpm[c] = best[0]
         pipe_c[c] = best[1]
         ovl_c[c] = best[3]
+        pack_c[c] = best[5]
         if best[3]:
             ovl_at_g[c] = {G: min((x for x in ovl if x[2] == G), key=lambda x: x[4])[3]
                            for G in sorted({x[2] for x in ovl})}
         # per market-step cost when the class fills the GPU alone
         cost[c] = best[4] * 1e6 / (len(probe) * Sp) * ncu
         cached[key] = {"waves_per_market": wpm[c], "pipelined": bool(pipe_c[c]), "overlap": ovl_c[c],
-                       "ns_per_market_step": cost[c]}
+                       "pack": pack_c[c], "ns_per_market_step": cost[c]}
     # waves per workgroup on the whole ensemble; classes that asked for more waves per market
     # than a candidate group holds are clamped to it
     # (an overlapped class runs, at each candidate, the clearing share that was fastest at
@@ -175,7 +190,8 @@ def tune(descs, seed=0, S_probe=None, min_markets=None, cache=None, arch="gfx950
         ovl_g = {c: ovl_at_g.get(c, {}).get(G, k) for c, k in ovl_c.items() if k}
         tn = {"waves_per_group": G, "waves_per_market": {int(c): min(w, G) for c, w in wpm.items()},
               "pipelined": {int(c): 1 for c, p in pipe_c.items() if p},
-              "overlap": {int(c): k for c, k in ovl_g.items()}}
+              "overlap": {int(c): k for c, k in ovl_g.items()},
+              "pack": {int(c): P for c, P in pack_c.items() if P}}
         ms = _time_launch(descs, seed, tn, S_probe or probe_steps(descs))
         if log:
             log("waves_per_group %2d: %.3f ms" % (G, ms))
@@ -196,6 +212,7 @@ def tune(descs, seed=0, S_probe=None, min_markets=None, cache=None, arch="gfx950
               "waves_per_market": {int(c): int(w) for c, w in wpm.items()},
               "pipelined": {int(c): 1 for c, p in pipe_c.items() if p},
               "overlap": {int(c): int(k) for c, k in ovl_c.items() if k},
+              "pack": {int(c): int(P) for c, P in pack_c.items() if P},
               "class_cost_ns": {int(c): float(v) for c, v in cost.items()},
               "tune_seconds": time.perf_counter() - t0}
     return result

@@ -1447,9 +1447,255 @@ __device__ __forceinline__ void run_pair(const EngineArgs &args, const Item &ite
     }
 }
 
-// FULL: some market may use the mid-price model; TRACE: record the per-step series.  Each
-// instantiation carries only the code it needs, which keeps scalar registers for the step loop.
-template <int TPL_MAX, bool FULL, bool TRACE>
+// ------------------------------------------------------------------------------------------
+// Packed small markets: P = 64 / SEG markets share one wave, market k of the wave owning the
+// lane segment [k SEG, k SEG + SEG).  A segment generates its market's orders in rows of SEG
+// agents and clears its book with SEG lanes of TPL ticks each, so a market of 16 agents no longer
+// leaves 48 lanes of its wave idle in every step, and P books clear in one pass.  The clearing is
+// clear_small's on a lane segment: the scan stops at the segment's edge, and each lane reads its
+// own segment's crossing lane, totals and best quotes by a lane permute instead of a readlane.
+// Last-tick model with the Philox generator (the host packs no other market); every value that
+// is wave-uniform elsewhere (the market, its descriptor, state and step counter, the generator's
+// per-step rounds) is per lane here, so the whole Philox evaluation runs per agent.
+// ------------------------------------------------------------------------------------------
+
+// Inclusive scans of x and y within lane segments of 2^SEGLOG lanes (SEGLOG 4 or 5).
+template <int SEGLOG>
+__device__ __forceinline__ void seg_scan_add2(uint32_t &x, uint32_t &y)
+{
+    x += dpp<0x111, 0xf>(x);
+    y += dpp<0x111, 0xf>(y);
+    x += dpp<0x112, 0xf>(x);
+    y += dpp<0x112, 0xf>(y);
+    x += dpp<0x114, 0xf>(x);
+    y += dpp<0x114, 0xf>(y);
+    x += dpp<0x118, 0xf>(x);
+    y += dpp<0x118, 0xf>(y);
+    if constexpr (SEGLOG >= 5) {
+        x += dpp<0x142, 0xa>(x);
+        y += dpp<0x142, 0xa>(y);
+    }
+}
+
+// x of lane l (any lane of the wave; l may differ between lanes)
+__device__ __forceinline__ uint32_t lane_value(uint32_t x, uint32_t l)
+{
+    return (uint32_t)__builtin_amdgcn_ds_bpermute((int)(l << 2), (int)x);
+}
+
+// The bits of a wave-wide mask that belong to this lane's segment (segment base `base`).
+template <int SEGLOG>
+__device__ __forceinline__ uint32_t seg_bits(uint64_t mask, uint32_t base)
+{
+    constexpr uint32_t kSeg = 1u << SEGLOG;
+    return (uint32_t)(mask >> base) & (uint32_t)((1ull << kSeg) - 1ull);
+}
+
+// First lane of this lane's segment where a predicate that holds on a suffix of the segment is
+// true, or the segment's last lane when it holds nowhere (as crossing_lane, per segment).
+template <int SEGLOG>
+__device__ __forceinline__ uint32_t seg_crossing_lane(bool pred, uint32_t base)
+{
+    constexpr uint32_t kSeg = 1u << SEGLOG;
+    return base + (uint32_t)__builtin_ctz(seg_bits<SEGLOG>(ballot(pred), base) | (1u << (kSeg - 1u)));
+}
+
+// One clearing pass over the book of each lane segment (bk: this lane's book, pairs for ticks
+// [0, SEG TPL), zero beyond L; ll: the lane's index in its segment; wr: the segment holds a
+// market, so its residual book is written back).  Segment-uniform result.
+template <int TPL, int SEGLOG>
+__device__ __forceinline__ ClearOut clear_seg(uint32_t *__restrict__ bk, uint32_t ll, uint32_t base, bool wr)
+{
+    constexpr uint32_t kSeg = 1u << SEGLOG;
+    const uint32_t q0 = ll * TPL;
+    uint32_t b[TPL], k[TPL];
+    load_pairs<TPL>(bk, q0, b, k);
+    uint32_t sb = 0, sa = 0;
+#pragma unroll
+    for (int j = 0; j < TPL; ++j) {
+        sb += b[j];
+        sa += k[j];
+    }
+    uint32_t ib = sb, ia = sa;
+    seg_scan_add2<SEGLOG>(ib, ia);
+    const uint32_t Tb = lane_value(ib, base + kSeg - 1u);
+    uint32_t D[TPL + 1], Sq[TPL];
+    D[0] = Tb - (ib - sb);
+    const uint32_t Sb = ia - sa;
+#pragma unroll
+    for (int j = 0; j < TPL; ++j) {
+        D[j + 1] = D[j] - b[j];
+        Sq[j] = (j ? Sq[j - 1] : Sb) + k[j];
+    }
+    uint32_t vc = Sb;
+#pragma unroll
+    for (int j = 0; j < TPL; ++j) vc = max(vc, min(D[j], Sq[j]));
+    ClearOut out;
+    out.v = lane_value(vc, seg_crossing_lane<SEGLOG>(Sq[TPL - 1] >= D[TPL - 1], base));
+    const uint32_t vs = out.v;
+    {
+        uint32_t pj = q0;
+#pragma unroll
+        for (int j = 0; j < TPL; ++j) pj += Sq[j] < vs ? 1u : 0u;
+        out.p = lane_value(pj, seg_crossing_lane<SEGLOG>(Sq[TPL - 1] >= vs, base));
+    }
+    uint32_t md = min(D[0], vs), ms = min(Sb, vs);
+#pragma unroll
+    for (int j = 0; j < TPL; ++j) {
+        const uint32_t md1 = min(D[j + 1], vs), ms1 = min(Sq[j], vs);
+        b[j] -= md - md1;
+        k[j] -= ms1 - ms;
+        md = md1;
+        ms = ms1;
+    }
+    if (wr) store_pairs<TPL>(bk, q0, b, k);
+    uint32_t hb = kNone, la = kNone;
+#pragma unroll
+    for (int j = 0; j < TPL; ++j)
+        if (b[j] != 0) hb = q0 + j;
+#pragma unroll
+    for (int j = TPL - 1; j >= 0; --j)
+        if (k[j] != 0) la = q0 + j;
+    const uint32_t mb = seg_bits<SEGLOG>(ballot(hb != kNone), base);
+    const uint32_t ma = seg_bits<SEGLOG>(ballot(la != kNone), base);
+    const uint32_t bbv = lane_value(hb, base + (mb ? 31u - (uint32_t)__builtin_clz(mb) : 0u));
+    const uint32_t bav = lane_value(la, base + (ma ? (uint32_t)__builtin_ctz(ma) : 0u));
+    out.bb = mb ? bbv : kNone;
+    out.ba = ma ? bav : kNone;
+    return out;
+}
+
+template <int SEGLOG>
+__device__ __forceinline__ ClearOut clear_seg_dispatch(uint32_t *bk, uint32_t tpl, uint32_t ll, uint32_t base,
+                                                       bool wr)
+{
+    if (tpl >= 4u) return clear_seg<4, SEGLOG>(bk, ll, base, wr);
+    if (tpl == 2u) return clear_seg<2, SEGLOG>(bk, ll, base, wr);
+    return clear_seg<1, SEGLOG>(bk, ll, base, wr);
+}
+
+// All S steps of the packed markets of one wave (wave `wave` of the item takes markets
+// wave P .. wave P + P - 1 of it).  item.share = P, item.hwords = ticks per lane of the segments.
+template <int SEGLOG, bool TRACE>
+__device__ __forceinline__ void run_packed_seg(const EngineArgs &args, const Item &item, uint32_t wave,
+                                               uint32_t lane, uint32_t *lds)
+{
+    constexpr uint32_t kSeg = 1u << SEGLOG;
+    constexpr uint32_t kP = 64u / kSeg;
+    const uint32_t seg = lane >> SEGLOG, ll = lane & (kSeg - 1u), base = seg << SEGLOG;
+    const uint32_t slot = wave * kP + seg;
+    const bool active = slot < item.count;
+    const uint32_t tpl = item.hwords;
+    uint32_t *bk = lds + (active ? slot : 0u) * item.stride;
+    // the integer statistics live in the slot's scratch words (64-bit LDS adds by the segment's
+    // first lane), which keeps registers for the per-lane generator and clearing
+    uint64_t *acc = reinterpret_cast<uint64_t *>(bk + item.stride - kScr);
+    uint32_t m = 0;
+    DevMarket d{};
+    uint32_t last = 0, prev = 0, s0 = 0;
+    double sum_r = 0.0, sum_r2 = 0.0;
+    if (active) {
+        m = args.order[item.first + slot];
+        d = args.desc[m];
+        const cae_state *st = args.state + m;
+        last = st->last;
+        prev = st->prev;
+        s0 = (uint32_t)st->steps_done;
+        sum_r = st->sum_r;
+        sum_r2 = st->sum_r2;
+        if (ll < 5u) acc[ll] = (&st->n_trade)[ll];  // n_trade, sum_vol, sum_px, sum_spread, n_spread
+        const uint32_t *gb = args.book + d.book_off;
+        for (uint32_t q = ll; q < kSeg * tpl; q += kSeg) {
+            uint2 v = make_uint2(0u, 0u);
+            if (q < d.L) {
+                v.x = gb[q];
+                v.y = gb[d.L + q];
+            }
+            reinterpret_cast<uint2 *>(bk)[q] = v;
+        }
+    }
+    wave_sync();
+    const double *lnT = args.lnT + d.L;  // ln(L + tick)
+    const uint32_t A = active ? d.A : 0u;
+    for (uint32_t i = 0; i < args.S; ++i) {
+        const uint32_t s = s0 + i;
+        {
+            const OrderCtx o = order_ctx<false>(d, s, Refs{last, prev, 2u * last, 0u});
+            const PhiloxStep gen(s, d.id, args.k0, args.k1);
+            // rows of SEG agents until every segment's market is done (the markets of a wave
+            // may have different populations)
+            for (uint32_t b0 = 0;; b0 += kSeg) {
+                const uint32_t a = b0 + ll;
+                const bool on = a < A;
+                if (!ballot(on)) break;
+                if (on) {
+                    uint32_t w0, w1, w2, w3 = 0;
+                    gen.words4(a, w0, w1, w2, w3);
+                    const uint32_t w = a >= o.n_noise ? other_word<false>(o, a, w0, w3) : noise_word(o, w0, w1);
+                    atomicAdd(&bk[w], order_qty(o, w2));
+                }
+            }
+        }
+        wave_sync();
+        // a segment without a market reads slot 0's book (its lanes point there) but writes
+        // nothing
+        const ClearOut co = clear_seg_dispatch<SEGLOG>(bk, tpl, ll, base, active);
+        if (active) {
+            prev = last;
+            if (co.v != 0) last = co.p;
+            if (ll == 0) {
+                if (co.v != 0) {
+                    atomicAdd(reinterpret_cast<unsigned long long *>(acc), 1ull);
+                    atomicAdd(reinterpret_cast<unsigned long long *>(acc + 1), (unsigned long long)co.v);
+                    atomicAdd(reinterpret_cast<unsigned long long *>(acc + 2), (unsigned long long)co.p);
+                }
+                if (co.bb != kNone && co.ba != kNone) {
+                    atomicAdd(reinterpret_cast<unsigned long long *>(acc + 3), (unsigned long long)(co.ba - co.bb));
+                    atomicAdd(reinterpret_cast<unsigned long long *>(acc + 4), 1ull);
+                }
+            }
+            const double r = lnT[last] - lnT[prev];
+            sum_r = sum_r + r;
+            sum_r2 = sum_r2 + r * r;
+            if constexpr (TRACE) {
+                if (ll == 0) trace_step(args, m, i, last, co.v);
+            }
+        }
+        wave_sync();
+    }
+    if (active) {
+        uint32_t *gb = args.book + d.book_off;
+        for (uint32_t q = ll; q < d.L; q += kSeg) {
+            const uint2 v = reinterpret_cast<const uint2 *>(bk)[q];
+            gb[q] = v.x;
+            gb[d.L + q] = v.y;
+        }
+        cae_state *st = args.state + m;
+        if (ll < 5u) (&st->n_trade)[ll] = acc[ll];
+        if (ll == 0) {
+            st->last = last;
+            st->prev = prev;
+            st->steps_done += args.S;
+            st->sum_r = sum_r;
+            st->sum_r2 = sum_r2;
+            st->ref2 = 2u * prev;  // twice the reference of the call's last step
+        }
+    }
+}
+
+template <bool TRACE>
+__device__ __forceinline__ void run_packed(const EngineArgs &args, const Item &item, uint32_t wave, uint32_t lane,
+                                           uint32_t *lds)
+{
+    if (item.share == 4u) run_packed_seg<4, TRACE>(args, item, wave, lane, lds);
+    else run_packed_seg<5, TRACE>(args, item, wave, lane, lds);
+}
+
+// FULL: some market may use the mid-price model; TRACE: record the per-step series; PACK: some
+// items hold packed small markets (their per-lane generator and clearing need more vector
+// registers, so only ensembles that use them run this code).  Each instantiation carries only
+// the code it needs, which keeps registers for the step loop.
+template <int TPL_MAX, bool FULL, bool TRACE, bool PACK>
 __global__ void __launch_bounds__(1024) cae_engine_kernel(const EngineArgs args)
 {
     extern __shared__ __align__(16) uint32_t lds[];
@@ -1471,6 +1717,8 @@ __global__ void __launch_bounds__(1024) cae_engine_kernel(const EngineArgs args)
         const bool active = sub < item.count;
         if (item.pipe == 1u) {
             run_pair<TPL_MAX, FULL, TRACE>(args, item, wave, lane, blockDim.x >> 6, lds);
+        } else if (PACK && item.pipe == 3u) {
+            if constexpr (PACK) run_packed<TRACE>(args, item, wave, lane, lds);
         } else if (item.wpm_log2 == 0) {
             if (active) run_market<TPL_MAX, false, FULL, TRACE>(args, item, sub, w_in, lane, true, lds);
         } else if (item.pipe == 2u) {
@@ -1751,24 +1999,29 @@ int device_cus(int dev, uint32_t *num_cu)
 
 using EngineFn = void (*)(const EngineArgs);
 
+// Packed items exist only in ensembles whose books all have at most kPackMaxL ticks (so the
+// packed instantiations are those of small books).
+constexpr uint32_t kPackMaxL = 128;
+
 template <bool FULL, bool TRACE>
-EngineFn engine_fn_t(uint32_t tpl_max)
+EngineFn engine_fn_t(uint32_t tpl_max, bool pack)
 {
+    if (pack) return tpl_max <= 1 ? cae_engine_kernel<1, FULL, TRACE, true> : cae_engine_kernel<2, FULL, TRACE, true>;
     switch (tpl_max) {
-    case 1: return cae_engine_kernel<1, FULL, TRACE>;
-    case 2: return cae_engine_kernel<2, FULL, TRACE>;
-    case 4: return cae_engine_kernel<4, FULL, TRACE>;
-    case 8: return cae_engine_kernel<8, FULL, TRACE>;
-    default: return cae_engine_kernel<16, FULL, TRACE>;
+    case 1: return cae_engine_kernel<1, FULL, TRACE, false>;
+    case 2: return cae_engine_kernel<2, FULL, TRACE, false>;
+    case 4: return cae_engine_kernel<4, FULL, TRACE, false>;
+    case 8: return cae_engine_kernel<8, FULL, TRACE, false>;
+    default: return cae_engine_kernel<16, FULL, TRACE, false>;
     }
 }
 
 // The instantiation for the largest book, with mid-price code only when some market uses that
-// model and trace stores only for cae_step_traced.
-EngineFn engine_fn(uint32_t tpl_max, bool mid, bool trace)
+// model, trace stores only for cae_step_traced and the packed path only when items use it.
+EngineFn engine_fn(uint32_t tpl_max, bool mid, bool trace, bool pack)
 {
-    if (mid) return trace ? engine_fn_t<true, true>(tpl_max) : engine_fn_t<true, false>(tpl_max);
-    return trace ? engine_fn_t<false, true>(tpl_max) : engine_fn_t<false, false>(tpl_max);
+    if (mid) return trace ? engine_fn_t<true, true>(tpl_max, pack) : engine_fn_t<true, false>(tpl_max, pack);
+    return trace ? engine_fn_t<false, true>(tpl_max, pack) : engine_fn_t<false, false>(tpl_max, pack);
 }
 
 uint32_t auto_wpm(uint32_t L, uint32_t A)
@@ -1794,6 +2047,7 @@ struct cae_ensemble {
     Layout lay{};
     uint32_t n_items = 0, tpl_max = 1, waves_per_group = 1, lds_bytes = 0, grid = 0;
     bool any_mid = false;  // some market uses the mid-price model or the SplitMix64 generator
+    bool any_pack = false; // some item holds packed small markets
     cae_tuning tuning{};
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     bool have_timing = false;
@@ -1814,9 +2068,24 @@ int build_schedule(cae_ensemble *e, const cae_tuning *tn, const uint32_t *ids,
     for (uint32_t m = 0; m < M; ++m)
         e->any_mid |= (e->desc[m].flags & CAE_MODEL_MASK) == CAE_MODEL_MID ||
                       ((e->desc[m].flags >> CAE_GEN_SHIFT) & 0xFFu) == CAE_GEN_SPLITMIX;
+    std::vector<uint32_t> packp(M, 0u);
+    for (uint32_t c = 0; c < CAE_NUM_CLASSES; ++c)
+        if (t.pack[c] != 0 && t.pack[c] != 2 && t.pack[c] != 4) return fail(CAE_EINVAL, "pack[%u] must be 0, 2 or 4", c);
+    uint32_t maxL = 0;
+    for (uint32_t m = 0; m < M; ++m) maxL = std::max(maxL, e->desc[m].L);
+    e->any_pack = false;
     for (uint32_t m = 0; m < M; ++m) {
         const cae_market &d = e->desc[m];
         const uint32_t c = lclass(d.L) * 8u + aclass(d.A);
+        // packed: last-tick Philox markets whose book fits 4 ticks per lane of a segment, in an
+        // ensemble of small books
+        const uint32_t P = maxL <= kPackMaxL ? t.pack[c] : 0u;
+        if (P && (d.flags & 0xFFFFu) == 0u && d.L <= 256u / P) {
+            packp[m] = P;
+            wpm[m] = 1;
+            e->any_pack = true;
+            continue;
+        }
         uint32_t w = t.waves_per_market[c];
         if (w == 0) w = auto_wpm(d.L, d.A);
         if (w > 16 || (w & (w - 1)) != 0) return fail(CAE_EINVAL, "waves_per_market[%u]=%u not a power of 2 <= 16", c, w);
@@ -1827,6 +2096,13 @@ int build_schedule(cae_ensemble *e, const cae_tuning *tn, const uint32_t *ids,
         if (w < 2) t.overlap[c] = 0;
         wpm_max = std::max(wpm_max, w);
         tpl_max = std::max(tpl_max, tpl_for(d.L));
+    }
+    {  // report packing only for the classes it applies to
+        bool used[CAE_NUM_CLASSES] = {};
+        for (uint32_t m = 0; m < M; ++m)
+            if (packp[m]) used[lclass(e->desc[m].L) * 8u + aclass(e->desc[m].A)] = true;
+        for (uint32_t c = 0; c < CAE_NUM_CLASSES; ++c)
+            if (!used[c]) t.pack[c] = 0;
     }
     uint32_t G = t.waves_per_group;
     if (G == 0) G = std::max(wpm_max, 4u);
@@ -1859,16 +2135,27 @@ int build_schedule(cae_ensemble *e, const cae_tuning *tn, const uint32_t *ids,
     std::vector<std::pair<double, Bin>> done;
     for (uint32_t idx = 0; idx < M; ++idx) {
         const uint32_t m = order[idx];
-        const uint32_t w = wpm[m], tp = tpl_for(e->desc[m].L);
+        const uint32_t w = wpm[m];
+        uint32_t tp = tpl_for(e->desc[m].L);
         const uint32_t c = lclass(e->desc[m].L) * 8u + aclass(e->desc[m].A);
         // overlapped markets keep two buffers of bins in LDS; wider offset ranges run plain
         const bool mid = (e->desc[m].flags & CAE_MODEL_MASK) == CAE_MODEL_MID;
         const uint32_t ov = e->desc[m].K <= (mid ? kMaxOverlapKMid : kMaxOverlapK) ? t.overlap[c] : 0u;
-        const uint32_t pp = t.pipelined[c] ? 1u : (ov ? 2u : 0u);
-        const uint32_t share = ov ? ov - 1u : 0u;
-        const uint32_t hw = ov ? hwords_for(e->desc[m].K, mid) : 0u;
-        const uint32_t stride = 2u * 64u * tp + 2u * hw + kScr;
+        uint32_t pp = t.pipelined[c] ? 1u : (ov ? 2u : 0u);
+        uint32_t share = ov ? ov - 1u : 0u;
+        uint32_t hw = ov ? hwords_for(e->desc[m].K, mid) : 0u;
+        uint32_t stride = 2u * 64u * tp + 2u * hw + kScr;
         uint32_t cap = pp == 1u ? 2u : G / w;
+        if (packp[m]) {  // P markets per wave, books of seg * hw ticks (hw ticks per lane)
+            const uint32_t seg = 64u / packp[m];
+            pp = 3u;
+            share = packp[m];
+            hw = 1u;
+            while (seg * hw < e->desc[m].L) hw <<= 1;
+            tp = 0u;
+            stride = 2u * seg * hw + kScr;
+            cap = G * packp[m];
+        }
         cap = std::max(1u, std::min(cap, lds_budget / (stride * 4u)));
         Bin *b = nullptr;
         for (auto &x : open)
@@ -1903,7 +2190,7 @@ int build_schedule(cae_ensemble *e, const cae_tuning *tn, const uint32_t *ids,
         it.first = (uint32_t)order.size();
         it.count = (uint32_t)b.ms.size();
         it.wpm_log2 = (uint32_t)__builtin_ctz(b.wpm);
-        it.stride = 2u * 64u * b.tpl + 2u * b.hw + kScr;
+        it.stride = b.pipe == 3u ? 2u * (64u / b.share) * b.hw + kScr : 2u * 64u * b.tpl + 2u * b.hw + kScr;
         it.pipe = b.pipe;
         it.share = b.share;
         it.hoff = 2u * 64u * b.tpl;
@@ -1940,7 +2227,7 @@ int build_schedule(cae_ensemble *e, const cae_tuning *tn, const uint32_t *ids,
     int rc = device_cus(e->device, &ncu);
     if (rc) return rc;
     int per_cu = 0;
-    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(engine_fn(tpl_max, e->any_mid, false)),
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(engine_fn(tpl_max, e->any_mid, false, e->any_pack)),
                                                          (int)(G * 64u), (size_t)lds_max));
     if (per_cu < 1) return fail(CAE_EINVAL, "schedule does not fit on a CU (lds %u B, %u waves)", lds_max, G);
     if (t.groups_per_cu) per_cu = std::min<int>(per_cu, (int)t.groups_per_cu);
@@ -2093,7 +2380,8 @@ static int step_impl(cae_ensemble *e, uint32_t S, bool naive, uint32_t *tr_price
     if (naive)
         hipLaunchKernelGGL(cae_naive_kernel, dim3((e->M + 63u) / 64u), dim3(64), 0, e->stream, a, e->M);
     else
-        hipLaunchKernelGGL(engine_fn(e->tpl_max, e->any_mid, tr_price != nullptr || tr_vol != nullptr), dim3(e->grid), dim3(e->waves_per_group * 64u), e->lds_bytes,
+        hipLaunchKernelGGL(engine_fn(e->tpl_max, e->any_mid, tr_price != nullptr || tr_vol != nullptr, e->any_pack),
+                           dim3(e->grid), dim3(e->waves_per_group * 64u), e->lds_bytes,
                            e->stream, a);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipEventRecord(e->ev1, e->stream));

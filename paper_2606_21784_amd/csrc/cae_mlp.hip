@@ -346,6 +346,290 @@ __global__ void __launch_bounds__(256) mlp_predict(const PredArgs a)
     }
 }
 
+// ------------------------------------------------------------------------------------------
+// Fused training step: forward, loss gradient, back-propagation and Adam in two launches, on
+// gfx950's v_mfma_f32_16x16x32_bf16 (eight bfloat16 of the reduction per lane and operand).
+//
+// mlp_train_rows: one workgroup per 16 batch rows.  The rows' input, both hidden activations,
+//   their pre-activations, the loss gradient and the first back-propagated gradient stay in LDS;
+//   every operand fragment is one 16-byte read (LDS rows, the bfloat16 W2 and its transposed
+//   copy).  The activations and gradients the weight gradients need are written to the
+//   workspace transposed ([feature][batch], 8-byte stores), so that the next kernel reads its
+//   fragments (eight consecutive batch rows) with 16-byte loads as well.
+// mlp_train_params: one wave per 16x16 tile of a weight gradient (with the bias as the extra row
+//   of ones, as in the unfused path), reduced over the whole batch in a fixed order by the wave
+//   that owns it -- no split-K partials, deterministic -- followed in the same wave by Adam and
+//   the bfloat16 copies of the updated weights.
+// Rounding points and fp32 accumulation are those of the unfused kernels; only the order of the
+// fp32 sums differs.
+// ------------------------------------------------------------------------------------------
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+constexpr uint32_t kTrainRows = 16;
+constexpr uint32_t kTrainMaxH = 256;
+constexpr uint32_t kTrainMaxIn = 32;
+constexpr uint32_t kTrainPad = 8;  // bf16 elements of padding per LDS row
+
+__device__ __forceinline__ v8bf ld8(const uint16_t *p)  // eight bfloat16, 16-byte aligned
+{
+    return __builtin_bit_cast(v8bf, *reinterpret_cast<const uint4 *>(p));
+}
+
+__device__ __forceinline__ v8bf pack8(const uint16_t (&e)[8])
+{
+    uint4 u;
+    u.x = (uint32_t)e[0] | ((uint32_t)e[1] << 16);
+    u.y = (uint32_t)e[2] | ((uint32_t)e[3] << 16);
+    u.z = (uint32_t)e[4] | ((uint32_t)e[5] << 16);
+    u.w = (uint32_t)e[6] | ((uint32_t)e[7] << 16);
+    return __builtin_bit_cast(v8bf, u);
+}
+
+__device__ __forceinline__ v4f mfma32(v8bf a, v8bf b, v4f c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// four bfloat16 of consecutive batch rows into a transposed [feature][batch] array
+__device__ __forceinline__ void st4(uint16_t *p, uint16_t a, uint16_t b, uint16_t c, uint16_t d)
+{
+    *reinterpret_cast<uint2 *>(p) = make_uint2((uint32_t)a | ((uint32_t)b << 16), (uint32_t)c | ((uint32_t)d << 16));
+}
+
+struct TrainArgs {
+    const float *x, *t;      // all samples: x[n][din], t[n][dout]
+    const uint32_t *idx;     // the batch's sample indices (NULL: 0..B-1)
+    uint32_t B, Bp;          // batch, and batch rounded up to 32 (leading dim of the T arrays)
+    uint32_t din, H, dout;
+    const uint16_t *W1, *W2, *W2T, *W3;
+    float *p, *m, *v, *grads;  // fp32 parameters, Adam moments, optional gradient output
+    uint16_t *wb;              // bfloat16 weight copies
+    uint16_t *xT, *h1T, *h2T, *dyT, *dz2T, *dz1T;
+    float *loss_part, *loss;
+    Layout l;
+    int kind;
+    float delta, inv_n;        // Huber delta; 1 / (B dout)
+    float lr, beta1, beta2, eps, c1, c2;
+    uint32_t tiles1, tiles2, tiles3;  // gradient tiles of W1|b1, W2|b2, W3|b3
+};
+
+__global__ void __launch_bounds__(256) mlp_train_rows(const TrainArgs a)
+{
+    extern __shared__ __align__(16) unsigned char tlds[];
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+    const uint32_t r = lane & 15u, g = lane >> 4;
+    const uint32_t row0 = blockIdx.x * kTrainRows;
+    const uint32_t H = a.H, ldh = H + kTrainPad, ct = H / 16u;
+    uint16_t *xs = reinterpret_cast<uint16_t *>(tlds);  // [16][32]
+    uint16_t *dys = xs + kTrainRows * 32u;               // [16][32]
+    uint16_t *h1s = dys + kTrainRows * 32u;              // [16][ldh]
+    uint16_t *h2s = h1s + kTrainRows * ldh;
+    uint16_t *dzs = h2s + kTrainRows * ldh;
+    float *z1s = reinterpret_cast<float *>(dzs + kTrainRows * ldh);  // [16][H]
+    float *z2s = z1s + kTrainRows * H;
+    // inputs of the rows (zero past the batch), their transposed copy, and a zeroed dy tile
+    for (uint32_t i = threadIdx.x; i < kTrainRows * 32u; i += 256u) {
+        const uint32_t rr = i / 32u, c = i % 32u, row = row0 + rr;
+        uint16_t v = 0;
+        if (row < a.B && c < a.din) {
+            const uint32_t src = a.idx ? a.idx[row] : row;
+            v = f2bf(a.x[(size_t)src * a.din + c]);
+        }
+        xs[i] = v;
+        dys[i] = 0;
+        if (c < a.din) a.xT[(size_t)c * a.Bp + row] = v;
+    }
+    __syncthreads();
+    // layer 1: z1 = x W1 + b1, h1 = silu(z1)  (one reduction step: d_in <= 32)
+    for (uint32_t j = wave; j < ct; j += 4u) {
+        const uint32_t n = 16u * j + r;
+        uint16_t e[8];
+#pragma unroll
+        for (uint32_t t = 0; t < 8u; ++t) {
+            const uint32_t k = 8u * g + t;
+            e[t] = k < a.din ? a.W1[(size_t)k * H + n] : (uint16_t)0;
+        }
+        v4f acc = {0.f, 0.f, 0.f, 0.f};
+        acc = mfma32(ld8(xs + r * 32u + 8u * g), pack8(e), acc);
+        uint16_t hb[4];
+#pragma unroll
+        for (uint32_t t = 0; t < 4u; ++t) {
+            const uint32_t rr = 4u * g + t;
+            const float z = acc[t] + a.p[a.l.b1 + n];
+            z1s[rr * H + n] = z;
+            hb[t] = f2bf(silu(z));
+            h1s[rr * ldh + n] = hb[t];
+        }
+        st4(a.h1T + (size_t)n * a.Bp + row0 + 4u * g, hb[0], hb[1], hb[2], hb[3]);
+    }
+    __syncthreads();
+    // layer 2: z2 = h1 W2 + b2, B fragments from the transposed copy W2T[n][k]
+    for (uint32_t j = wave; j < ct; j += 4u) {
+        const uint32_t n = 16u * j + r;
+        v4f acc = {0.f, 0.f, 0.f, 0.f};
+        for (uint32_t k0 = 0; k0 < H; k0 += 32u)
+            acc = mfma32(ld8(h1s + r * ldh + k0 + 8u * g), ld8(a.W2T + (size_t)n * H + k0 + 8u * g), acc);
+        uint16_t hb[4];
+#pragma unroll
+        for (uint32_t t = 0; t < 4u; ++t) {
+            const uint32_t rr = 4u * g + t;
+            const float z = acc[t] + a.p[a.l.b2 + n];
+            z2s[rr * H + n] = z;
+            hb[t] = f2bf(silu(z));
+            h2s[rr * ldh + n] = hb[t];
+        }
+        st4(a.h2T + (size_t)n * a.Bp + row0 + 4u * g, hb[0], hb[1], hb[2], hb[3]);
+    }
+    __syncthreads();
+    // layer 3, loss and its gradient (one wave): y = h2 W3 + b3; dy = dloss/dy, zero past the batch
+    if (wave == 0) {
+        v4f acc = {0.f, 0.f, 0.f, 0.f};
+        for (uint32_t k0 = 0; k0 < H; k0 += 32u) {
+            uint16_t e[8];
+#pragma unroll
+            for (uint32_t t = 0; t < 8u; ++t)
+                e[t] = r < a.dout ? a.W3[(size_t)(k0 + 8u * g + t) * a.dout + r] : (uint16_t)0;
+            acc = mfma32(ld8(h2s + r * ldh + k0 + 8u * g), pack8(e), acc);
+        }
+        float ls = 0.f;
+        uint16_t db[4];
+#pragma unroll
+        for (uint32_t t = 0; t < 4u; ++t) {
+            const uint32_t rr = 4u * g + t, row = row0 + rr;
+            float dy = 0.f;
+            if (row < a.B && r < a.dout) {
+                const uint32_t src = a.idx ? a.idx[row] : row;
+                const float d = acc[t] + a.p[a.l.b3 + r] - a.t[(size_t)src * a.dout + r];
+                if (a.kind == CAE_LOSS_MSE) {
+                    dy = 2.0f * d * a.inv_n;
+                    ls += d * d;
+                } else {
+                    const float ad = fabsf(d);
+                    dy = fminf(fmaxf(d, -a.delta), a.delta) * a.inv_n;
+                    ls += ad <= a.delta ? 0.5f * d * d : a.delta * (ad - 0.5f * a.delta);
+                }
+            }
+            db[t] = f2bf(dy);
+            dys[rr * 32u + r] = db[t];
+        }
+        st4(a.dyT + (size_t)r * a.Bp + row0 + 4u * g, db[0], db[1], db[2], db[3]);
+        // the rows' loss, summed over the wave in a fixed order
+#pragma unroll
+        for (uint32_t off = 32u; off > 0u; off >>= 1) ls += __shfl_xor(ls, (int)off);
+        if (lane == 0) a.loss_part[blockIdx.x] = ls;
+    }
+    __syncthreads();
+    // dz2 = (dy W3^T) silu'(z2)  (one reduction step: d_out <= 16)
+    for (uint32_t j = wave; j < ct; j += 4u) {
+        const uint32_t n = 16u * j + r;
+        uint16_t e[8];
+#pragma unroll
+        for (uint32_t t = 0; t < 8u; ++t) {
+            const uint32_t k = 8u * g + t;
+            e[t] = k < a.dout ? a.W3[(size_t)n * a.dout + k] : (uint16_t)0;
+        }
+        v4f acc = {0.f, 0.f, 0.f, 0.f};
+        acc = mfma32(ld8(dys + r * 32u + 8u * g), pack8(e), acc);
+        uint16_t zb[4];
+#pragma unroll
+        for (uint32_t t = 0; t < 4u; ++t) {
+            const uint32_t rr = 4u * g + t;
+            zb[t] = f2bf(acc[t] * dsilu(z2s[rr * H + n]));
+            dzs[rr * ldh + n] = zb[t];
+        }
+        st4(a.dz2T + (size_t)n * a.Bp + row0 + 4u * g, zb[0], zb[1], zb[2], zb[3]);
+    }
+    __syncthreads();
+    // dz1 = (dz2 W2^T) silu'(z1): B fragments W2[n][k], eight consecutive k
+    for (uint32_t j = wave; j < ct; j += 4u) {
+        const uint32_t n = 16u * j + r;
+        v4f acc = {0.f, 0.f, 0.f, 0.f};
+        for (uint32_t k0 = 0; k0 < H; k0 += 32u)
+            acc = mfma32(ld8(dzs + r * ldh + k0 + 8u * g), ld8(a.W2 + (size_t)n * H + k0 + 8u * g), acc);
+        uint16_t zb[4];
+#pragma unroll
+        for (uint32_t t = 0; t < 4u; ++t) zb[t] = f2bf(acc[t] * dsilu(z1s[(4u * g + t) * H + n]));
+        st4(a.dz1T + (size_t)n * a.Bp + row0 + 4u * g, zb[0], zb[1], zb[2], zb[3]);
+    }
+}
+
+// One Adam update of parameter i with gradient gi (Kingma and Ba 2015, algorithm 1).
+__device__ __forceinline__ float adam_one(const TrainArgs &a, uint64_t i, float gi)
+{
+    const float mi = a.beta1 * a.m[i] + (1.0f - a.beta1) * gi;
+    const float vi = a.beta2 * a.v[i] + (1.0f - a.beta2) * gi * gi;
+    a.m[i] = mi;
+    a.v[i] = vi;
+    const float pi = a.p[i] - a.lr * (mi / a.c1) / (sqrtf(vi / a.c2) + a.eps);
+    a.p[i] = pi;
+    if (a.grads) a.grads[i] = gi;
+    return pi;
+}
+
+__global__ void __launch_bounds__(256) mlp_train_params(const TrainArgs a)
+{
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+    const uint32_t r = lane & 15u, g = lane >> 4;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {  // mean loss of the batch, partials in row order
+        float s = 0.f;
+        for (uint32_t i = 0; i < a.Bp / kTrainRows; ++i) s += a.loss_part[i];
+        a.loss[0] = s * a.inv_n;
+    }
+    uint32_t tile = blockIdx.x * 4u + wave;
+    const uint32_t H = a.H, din = a.din, dout = a.dout, ct = H / 16u;
+    // which gradient: [A^T ; 1] B over the batch, A the layer's input, B its output gradient
+    const uint16_t *AT, *BT;
+    uint32_t M, N, ti, tj;
+    uint64_t woff, boff, wcopy;
+    if (tile < a.tiles1) {
+        AT = a.xT, BT = a.dz1T, M = din, N = H, ti = tile / ct, tj = tile % ct;
+        woff = a.l.w1, boff = a.l.b1, wcopy = 0;
+    } else if ((tile -= a.tiles1) < a.tiles2) {
+        AT = a.h1T, BT = a.dz2T, M = H, N = H, ti = tile / ct, tj = tile % ct;
+        woff = a.l.w2, boff = a.l.b2, wcopy = (uint64_t)din * H;
+    } else if ((tile -= a.tiles2) < a.tiles3) {
+        AT = a.h2T, BT = a.dyT, M = H, N = dout, ti = tile, tj = 0;
+        woff = a.l.w3, boff = a.l.b3, wcopy = (uint64_t)din * H + (uint64_t)H * H;
+    } else {
+        return;
+    }
+    const uint32_t i = ti * 16u + r, j = tj * 16u + r;  // A row and B column this lane feeds
+    v8bf ones;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) ones[t] = (__bf16)1.0f;
+    v8bf zero;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) zero[t] = (__bf16)0.0f;
+    const bool arow = i < M, brow = j < N;  // rows >= Bp of the transposed arrays do not exist
+    const uint16_t *ap = AT + (size_t)(arow ? i : 0) * a.Bp + 8u * g;
+    const uint16_t *bp = BT + (size_t)(brow ? j : 0) * a.Bp + 8u * g;
+    v4f acc = {0.f, 0.f, 0.f, 0.f};
+    for (uint32_t b0 = 0; b0 < a.Bp; b0 += 32u) {
+        const v8bf av = arow ? ld8(ap + b0) : (i == M ? ones : zero);
+        const v8bf bv = brow ? ld8(bp + b0) : zero;
+        acc = mfma32(av, bv, acc);
+    }
+    const uint32_t jc = tj * 16u + r;
+    if (jc >= N) return;
+#pragma unroll
+    for (uint32_t t = 0; t < 4u; ++t) {
+        const uint32_t ic = ti * 16u + 4u * g + t;
+        if (ic > M) continue;
+        if (ic == M) {
+            adam_one(a, boff + jc, acc[t]);
+        } else {
+            const float pi = adam_one(a, woff + (uint64_t)ic * N + jc, acc[t]);
+            const uint16_t w = f2bf(pi);
+            a.wb[wcopy + (uint64_t)ic * N + jc] = w;
+            if (woff == a.l.w2) a.wb[a.l.w2t + (uint64_t)jc * H + ic] = w;
+        }
+    }
+}
+
+}  // namespace
+
+namespace {
+int forward_impl(const cae_mlp *net, const float *x, float *y, uint32_t N, void *ws, hipStream_t s);
 }  // namespace
 
 namespace cae_detail {
@@ -380,6 +664,28 @@ WsLayout ws_layout(uint32_t din, uint32_t H, uint32_t dout, uint32_t N)
     const uint64_t parts = std::min<uint64_t>(kMaxParts, (N + kSplitChunk - 1) / kSplitChunk);
     const uint64_t rows = std::max<uint64_t>(din, H) + 1;
     w.part = o; o = al(o + 4ull * parts * rows * std::max<uint32_t>(H, dout));
+    w.total = o;
+    return w;
+}
+
+// Workspace of the fused training step: the transposed activations and gradients ([rows][Bp]
+// bfloat16, Bp = the batch rounded up to 32) and one loss partial per 16 rows.
+struct TrainWs {
+    size_t xT, h1T, h2T, dyT, dz2T, dz1T, loss_part, total;
+};
+
+TrainWs train_ws(uint32_t din, uint32_t H, uint32_t N)
+{
+    const size_t Bp = (N + 31u) / 32u * 32u;
+    TrainWs w;
+    size_t o = 0;
+    w.xT = o; o = al(o + 2 * din * Bp);
+    w.h1T = o; o = al(o + 2 * (size_t)H * Bp);
+    w.h2T = o; o = al(o + 2 * (size_t)H * Bp);
+    w.dyT = o; o = al(o + 2 * 16 * Bp);
+    w.dz2T = o; o = al(o + 2 * (size_t)H * Bp);
+    w.dz1T = o; o = al(o + 2 * (size_t)H * Bp);
+    w.loss_part = o; o = al(o + 4 * (Bp / kTrainRows));
     w.total = o;
     return w;
 }
@@ -463,7 +769,8 @@ int cae_mlp_sizes(uint32_t d_in, uint32_t d_hidden, uint32_t d_out, uint32_t max
     const Layout l = layout(d_in, d_hidden, d_out);
     out->n_params = l.P;
     out->n_weights = l.W;
-    out->workspace_bytes = ws_layout(d_in, d_hidden, d_out, max_batch).total;
+    out->workspace_bytes = std::max(ws_layout(d_in, d_hidden, d_out, max_batch).total,
+                                    train_ws(d_in, d_hidden, max_batch).total);
     return CAE_OK;
 }
 
@@ -483,37 +790,7 @@ int cae_mlp_forward(const cae_mlp *net, const float *x, float *y, uint32_t N, vo
     if (rc) return rc;
     if (!x || !y || !ws) return mfail(CAE_EINVAL, "NULL x, y or workspace");
     if (N == 0) return CAE_OK;
-    hipStream_t s = (hipStream_t)stream;
-    const uint32_t din = net->d_in, H = net->d_hidden, dout = net->d_out;
-    const Layout l = layout(din, H, dout);
-    const WsLayout w = ws_layout(din, H, dout, N);
-    unsigned char *b = static_cast<unsigned char *>(ws);
-    uint16_t *xb = reinterpret_cast<uint16_t *>(b + w.xb);
-    float *z1 = reinterpret_cast<float *>(b + w.z1);
-    uint16_t *h1 = reinterpret_cast<uint16_t *>(b + w.h1);
-    float *z2 = reinterpret_cast<float *>(b + w.z2);
-    uint16_t *h2 = reinterpret_cast<uint16_t *>(b + w.h2);
-    const uint16_t *W1 = net->weights, *W2 = W1 + (size_t)din * H, *W3 = W2 + (size_t)H * H;
-    const uint64_t nx = (uint64_t)N * din;
-    hipLaunchKernelGGL(to_bf16, dim3((uint32_t)std::min<uint64_t>((nx + 255) / 256, 1024)), dim3(256), 0, s, x, xb, nx);
-    GemmArgs g = gargs(xb, din, W1, H, N, H, din);
-    g.bias = net->params + l.b1;
-    g.Of = z1;
-    g.Ob = h1;
-    g.ldo = H;
-    gemm<false, false, EPI_HIDDEN>(g, s);
-    g = gargs(h1, H, W2, H, N, H, H);
-    g.bias = net->params + l.b2;
-    g.Of = z2;
-    g.Ob = h2;
-    g.ldo = H;
-    gemm<false, false, EPI_HIDDEN>(g, s);
-    g = gargs(h2, H, W3, dout, N, dout, H);
-    g.bias = net->params + l.b3;
-    g.Of = y;
-    g.ldo = dout;
-    gemm<false, false, EPI_OUTPUT>(g, s);
-    return launch_status();
+    return forward_impl(net, x, y, N, ws, (hipStream_t)stream);
 }
 
 int cae_mlp_predict(const cae_mlp *net, const float *x, float *y, uint32_t N, void *stream)
@@ -604,6 +881,71 @@ int cae_mlp_adam(const cae_mlp *net, const float *grads, float *m, float *v, uin
     return launch_status();
 }
 
+int cae_mlp_train_step(const cae_mlp *net, const float *x, const float *target, const uint32_t *idx, uint32_t N,
+                       float *m, float *v, uint32_t step, float lr, float beta1, float beta2, float eps, int loss_kind,
+                       float delta, float *loss, float *grads, void *ws, void *stream)
+{
+    int rc = check_net(net);
+    if (rc) return rc;
+    const uint32_t din = net->d_in, H = net->d_hidden, dout = net->d_out;
+    if (H % 32u || H > kTrainMaxH || din > kTrainMaxIn)
+        return mfail(CAE_EINVAL, "cae_mlp_train_step needs d_hidden a multiple of 32 up to 256 and d_in <= 32");
+    if (!x || !target || !m || !v || !loss || !ws) return mfail(CAE_EINVAL, "NULL pointer");
+    if (N == 0) return mfail(CAE_EINVAL, "N must be >= 1");
+    if (step < 1) return mfail(CAE_EINVAL, "step counts from 1");
+    if (loss_kind != CAE_LOSS_MSE && loss_kind != CAE_LOSS_HUBER) return mfail(CAE_EINVAL, "unknown loss kind");
+    if (loss_kind == CAE_LOSS_HUBER && !(delta > 0.0f)) return mfail(CAE_EINVAL, "Huber delta must be > 0");
+    hipStream_t s = (hipStream_t)stream;
+    const Layout l = layout(din, H, dout);
+    const TrainWs w = train_ws(din, H, N);
+    unsigned char *b = static_cast<unsigned char *>(ws);
+    TrainArgs a;
+    a.x = x;
+    a.t = target;
+    a.idx = idx;
+    a.B = N;
+    a.Bp = (N + 31u) / 32u * 32u;
+    a.din = din;
+    a.H = H;
+    a.dout = dout;
+    a.W1 = net->weights;
+    a.W2 = a.W1 + (size_t)din * H;
+    a.W3 = a.W2 + (size_t)H * H;
+    a.W2T = net->weights + l.w2t;
+    a.p = net->params;
+    a.m = m;
+    a.v = v;
+    a.grads = grads;
+    a.wb = net->weights;
+    a.xT = reinterpret_cast<uint16_t *>(b + w.xT);
+    a.h1T = reinterpret_cast<uint16_t *>(b + w.h1T);
+    a.h2T = reinterpret_cast<uint16_t *>(b + w.h2T);
+    a.dyT = reinterpret_cast<uint16_t *>(b + w.dyT);
+    a.dz2T = reinterpret_cast<uint16_t *>(b + w.dz2T);
+    a.dz1T = reinterpret_cast<uint16_t *>(b + w.dz1T);
+    a.loss_part = reinterpret_cast<float *>(b + w.loss_part);
+    a.loss = loss;
+    a.l = l;
+    a.kind = loss_kind;
+    a.delta = delta;
+    a.inv_n = 1.0f / (float)((double)N * dout);
+    a.lr = lr;
+    a.beta1 = beta1;
+    a.beta2 = beta2;
+    a.eps = eps;
+    a.c1 = (float)(1.0 - std::pow((double)beta1, (double)step));
+    a.c2 = (float)(1.0 - std::pow((double)beta2, (double)step));
+    const uint32_t ct = H / 16u;
+    a.tiles1 = (din + 1u + 15u) / 16u * ct;
+    a.tiles2 = (H / 16u + 1u) * ct;
+    a.tiles3 = H / 16u + 1u;
+    const size_t lds = 2ull * (2u * kTrainRows * 32u + 3ull * kTrainRows * (H + kTrainPad)) + 8ull * kTrainRows * H;
+    hipLaunchKernelGGL(mlp_train_rows, dim3(a.Bp / kTrainRows), dim3(256), lds, s, a);
+    const uint32_t tiles = a.tiles1 + a.tiles2 + a.tiles3;
+    hipLaunchKernelGGL(mlp_train_params, dim3((tiles + 3u) / 4u), dim3(256), 0, s, a);
+    return launch_status();
+}
+
 int cae_mlp_loss_grad(const float *y, const float *target, float *dy, float *loss, uint32_t n, int kind, float delta,
                       void *stream)
 {
@@ -616,3 +958,44 @@ int cae_mlp_loss_grad(const float *y, const float *target, float *dy, float *los
 }
 
 }  // extern "C"
+
+namespace {
+
+// The unfused forward pass: x -> bf16, then three matrix-core layer products, activations kept in
+// ws (the prefix of ws_layout) for cae_mlp_backward.
+int forward_impl(const cae_mlp *net, const float *x, float *y, uint32_t N, void *ws, hipStream_t s)
+{
+    const uint32_t din = net->d_in, H = net->d_hidden, dout = net->d_out;
+    const Layout l = layout(din, H, dout);
+    const WsLayout w = ws_layout(din, H, dout, N);
+    unsigned char *b = static_cast<unsigned char *>(ws);
+    uint16_t *xb = reinterpret_cast<uint16_t *>(b + w.xb);
+    float *z1 = reinterpret_cast<float *>(b + w.z1);
+    uint16_t *h1 = reinterpret_cast<uint16_t *>(b + w.h1);
+    float *z2 = reinterpret_cast<float *>(b + w.z2);
+    uint16_t *h2 = reinterpret_cast<uint16_t *>(b + w.h2);
+    const uint16_t *W1 = net->weights, *W2 = W1 + (size_t)din * H, *W3 = W2 + (size_t)H * H;
+    const uint64_t nx = (uint64_t)N * din;
+    hipLaunchKernelGGL(to_bf16, dim3((uint32_t)std::min<uint64_t>((nx + 255) / 256, 1024)), dim3(256), 0, s, x, xb, nx);
+    GemmArgs g = gargs(xb, din, W1, H, N, H, din);
+    g.bias = net->params + l.b1;
+    g.Of = z1;
+    g.Ob = h1;
+    g.ldo = H;
+    gemm<false, false, EPI_HIDDEN>(g, s);
+    g = gargs(h1, H, W2, H, N, H, H);
+    g.bias = net->params + l.b2;
+    g.Of = z2;
+    g.Ob = h2;
+    g.ldo = H;
+    gemm<false, false, EPI_HIDDEN>(g, s);
+    g = gargs(h2, H, W3, dout, N, dout, H);
+    g.bias = net->params + l.b3;
+    g.Of = y;
+    g.ldo = dout;
+    gemm<false, false, EPI_OUTPUT>(g, s);
+    return launch_status();
+}
+
+}  // namespace
+

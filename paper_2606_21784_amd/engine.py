@@ -61,7 +61,7 @@ def sizes(descs):
 def tuning_struct(t=None):
     """A cae_tuning from a dict {waves_per_group, groups_per_cu, max_lds_bytes, flags,
     waves_per_market: {class: waves}, pipelined: {class: 1}, overlap: {class: k},
-    class_cost_ns: {class: ns}} (or None)."""
+    class_cost_ns: {class: ns}, pack: {class: 2 or 4}} (or None)."""
     if t is None:
         return None
     if isinstance(t, Tuning):
@@ -79,6 +79,8 @@ def tuning_struct(t=None):
         ts.overlap[int(c)] = int(v)
     for c, v in dict(t.get("class_cost_ns", {})).items():
         ts.class_cost[int(c)] = float(v)
+    for c, v in dict(t.get("pack", {})).items():
+        ts.pack[int(c)] = int(v)
     return ts
 
 
@@ -207,7 +209,8 @@ class Ensemble:
                 "pipelined": {c: 1 for c in range(_lib.NUM_CLASSES) if t.pipelined[c]},
                 "overlap": {c: int(t.overlap[c]) for c in range(_lib.NUM_CLASSES) if t.overlap[c]},
                 "class_cost_ns": {c: float(t.class_cost[c])
-                                  for c in range(_lib.NUM_CLASSES) if t.class_cost[c] > 0}}
+                                  for c in range(_lib.NUM_CLASSES) if t.class_cost[c] > 0},
+                "pack": {c: int(t.pack[c]) for c in range(_lib.NUM_CLASSES) if t.pack[c]}}
 
     def book_offsets(self):
         L = self.descs["L"].astype(np.uint64)

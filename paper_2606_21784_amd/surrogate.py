@@ -116,9 +116,12 @@ class TargetScaler:
         return np.exp(np.asarray(Z, dtype=np.float64) * self.sd + self.mu)
 
 
-def train(net, X, Z, epochs=300, batch=1024, lr=3e-3, lr_min=1e-5, seed=0, huber_delta=0.05, log=None):
+def train(net, X, Z, epochs=300, batch=1024, lr=3e-3, lr_min=1e-5, seed=0, huber_delta=0.05, log=None,
+          timing=None):
     """Adam on the Huber loss (huber_delta; None: squared error) of the log targets, cosine
-    learning rate."""
+    learning rate.  Each step is one ``cae_mlp_train_step`` call (two launches) on the rows a
+    per-epoch device permutation selects.  If timing is a dict, the mean wall time per step
+    (host launch rate, measured over the whole run) is stored in it."""
     import torch
     n = len(X)
     xd = torch.from_numpy(np.ascontiguousarray(X)).to(net.device)
@@ -129,18 +132,23 @@ def train(net, X, Z, epochs=300, batch=1024, lr=3e-3, lr_min=1e-5, seed=0, huber
     total = epochs * steps_per_epoch
     step = 0
     hist = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
     for ep in range(epochs):
-        perm = torch.randperm(n, device=net.device, generator=g)
+        perm = torch.randperm(n, device=net.device, generator=g).to(torch.int32)
         for b in range(steps_per_epoch):
-            idx = perm[b * batch:(b + 1) * batch]
             rate = lr_min + 0.5 * (lr - lr_min) * (1.0 + np.cos(np.pi * step / total))
-            net.train_step(xd[idx].contiguous(), zd[idx].contiguous(), float(rate),
-                           huber_delta=huber_delta)
+            net.train_step_fused(xd, zd, float(rate), idx=perm[b * batch:(b + 1) * batch],
+                                 huber_delta=huber_delta)
             step += 1
         if ep % max(1, epochs // 10) == 0 or ep == epochs - 1:
             hist.append((ep, float(net.loss.item())))
             if log:
                 log("epoch %d loss %.5f" % hist[-1])
+    torch.cuda.synchronize()
+    if timing is not None:
+        timing["steps"] = step
+        timing["us_per_step"] = 1e6 * (time.perf_counter() - t0) / max(step, 1)
     return hist
 
 
@@ -204,7 +212,8 @@ def fit_and_evaluate(data, epochs=300, hidden=256, batch=1024, lr=3e-3, huber_de
     Ztr = scaler.fwd(Ytr[ok_tr])
     net = mlp.MLP(4, hidden, 3, max_batch=8192, seed=0)
     t0 = time.perf_counter()
-    hist = train(net, Xtr, Ztr, epochs=epochs, batch=batch, lr=lr, huber_delta=huber_delta, log=log)
+    ttime = {}
+    hist = train(net, Xtr, Ztr, epochs=epochs, batch=batch, lr=lr, huber_delta=huber_delta, log=log, timing=ttime)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
     pred = predict(net, Xte, scaler)
@@ -243,6 +252,7 @@ def fit_and_evaluate(data, epochs=300, hidden=256, batch=1024, lr=3e-3, huber_de
         "linear_predictor_rel_err": summary(rel_err(lin_pred, Yte[ok_te])),
         "mc_noise_rel_diff": summary(noise),
         "generate_train_s": data["generate_train_s"], "train_s": train_s,
+        "train_steps": ttime.get("steps"), "train_us_per_step": ttime.get("us_per_step"),
         "train_loss": hist[-1][1], "epochs": epochs, "batch": batch, "lr": lr, "hidden": hidden,
         "huber_delta": huber_delta,
     }

@@ -37,7 +37,7 @@ def test_struct_layouts(cae):
     assert C.sizeof(cae.Market) == 32
     assert C.sizeof(cae.State) == 80
     assert C.sizeof(cae.Sizes) == 32
-    assert C.sizeof(cae.Tuning) == 16 + 7 * cae.NUM_CLASSES
+    assert C.sizeof(cae.Tuning) == 16 + 8 * cae.NUM_CLASSES
 
 
 def test_header_struct_sizes_match_binding(cae, tmp_path):

@@ -145,7 +145,8 @@ def test_loss_grad_matches_torch_autograd(delta):
     assert abs(float(net.loss.item()) - float(loss.item())) < 1e-5 * max(1.0, float(loss.item()))
 
 
-def test_training_fits_smooth_function():
+@pytest.mark.parametrize("fused", [False, True])
+def test_training_fits_smooth_function(fused):
     import torch
     M = _mlp()
     rng = np.random.default_rng(8)
@@ -158,11 +159,112 @@ def test_training_fits_smooth_function():
     first = None
     for epoch in range(60):
         perm = torch.randperm(4096, device="cuda")
+        pi = perm.to(torch.int32)
         for b in range(8):
             idx = perm[b * 512:(b + 1) * 512]
-            loss = net.train_step(xd[idx].contiguous(), td[idx].contiguous(), 2e-3)
+            if fused:
+                loss = net.train_step_fused(xd, td, 2e-3, idx=pi[b * 512:(b + 1) * 512])
+            else:
+                loss = net.train_step(xd[idx].contiguous(), td[idx].contiguous(), 2e-3)
         if first is None:
             first = float(loss.item())
     y = net.forward(xd[:512].contiguous())
     final = float(((y - td[:512]) ** 2).mean().item())
     assert final < 0.02 and final < first / 10, (first, final)
+
+
+def _huber_grad(y, t, delta, n):
+    r = y - t
+    if delta is None:
+        return 2.0 * r / n, float(np.sum(r * r) / n)
+    a = np.abs(r)
+    loss = np.where(a <= delta, 0.5 * r * r, delta * (a - 0.5 * delta))
+    return np.clip(r, -delta, delta) / n, float(loss.sum() / n)
+
+
+# The fused step (two launches): gradients against the oracle's back-propagation of the loss
+# gradient of the oracle's own forward pass (same bfloat16 rounding points), parameters against
+# the oracle's Adam fed the GPU's gradient, on a gathered batch (rows idx of a larger sample set).
+# Batches: the training batch (1024), ragged ones (1000, 37: padded to a multiple of 32 with rows
+# that must contribute nothing), a large one (4097), and another shape.
+@pytest.mark.parametrize("dims,N,delta", [((4, 256, 3), 1024, 0.05), ((4, 256, 3), 1000, None),
+                                          ((4, 256, 3), 37, 0.05), ((4, 256, 3), 4097, 0.7),
+                                          ((7, 64, 5), 600, 0.05), ((32, 32, 16), 33, None)])
+def test_fused_train_step_matches_oracle(dims, N, delta):
+    import torch
+    M = _mlp()
+    net = M.MLP(*dims, max_batch=N, seed=13)
+    rng = np.random.default_rng(14)
+    p0 = net.get_params().astype(np.float64)
+    d_in, H, d_out = dims
+    o = d_in * H
+    p0[o:o + H] = rng.normal(0, 0.1, H)  # nonzero biases
+    p0[o + H + H * H:o + 2 * H + H * H] = rng.normal(0, 0.1, H)
+    net.set_params(p0)
+    p0 = net.get_params().astype(np.float64)
+    m0 = rng.normal(0, 1e-3, p0.size)
+    v0 = rng.uniform(0, 1e-4, p0.size)
+    net.m.copy_(torch.from_numpy(m0.astype(np.float32)))
+    net.v.copy_(torch.from_numpy(v0.astype(np.float32)))
+    net.step_count = 4  # the call makes step 5
+    rows = N + 500
+    X = rng.normal(0, 1, (rows, d_in)).astype(np.float32)
+    T = rng.normal(0, 0.3, (rows, d_out)).astype(np.float32)
+    idx = rng.permutation(rows)[:N].astype(np.int32)
+    loss = net.train_step_fused(torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda(), 1e-3,
+                                idx=torch.from_numpy(idx).cuda(), huber_delta=delta, grads=True)
+    g = net.grads.cpu().numpy().astype(np.float64)
+    xb, tb = X[idx].astype(np.float64), T[idx].astype(np.float64)
+    y = OM.forward(p0, dims, xb, round_bf16=True)
+    dy, loss_ref = _huber_grad(y, tb, delta, N * d_out)
+    go = OM.backward(p0, dims, xb, dy, round_bf16=True)
+    for name, a, b in zip(["W1", "b1", "W2", "b2", "W3", "b3"], OM.split(g, dims), OM.split(go, dims)):
+        assert _rel(a, b) < 5e-3, (name, _rel(a, b))
+    assert abs(float(loss.item()) - loss_ref) <= 2e-3 * loss_ref
+    p1, m1, v1 = OM.adam(p0, g, m0.astype(np.float32).astype(np.float64),
+                         v0.astype(np.float32).astype(np.float64), 5, 1e-3)
+    np.testing.assert_allclose(net.get_params(), p1, rtol=1e-5, atol=1e-6)
+    np.testing.assert_allclose(net.m.cpu().numpy(), m1, rtol=1e-5, atol=1e-9)
+    # the kernels take 1 - beta2 in fp32: 1 - fp32(0.999) is 0.001 (1 + 1.3e-5), which the
+    # second moment inherits where the squared gradient dominates it
+    np.testing.assert_allclose(net.v.cpu().numpy(), v1, rtol=3e-5, atol=1e-12)
+    W = (net.weights.cpu().numpy().view(np.uint16).astype(np.uint32) << 16).view(np.float32)
+    W1, b1, W2, b2, W3, b3 = OM.split(net.get_params(), dims)
+    ref = np.concatenate([W1.ravel(), W2.ravel(), W3.ravel(), W2.T.ravel()])
+    np.testing.assert_array_equal(W, OM.bf16(ref).astype(np.float32))
+
+
+def test_fused_train_step_equals_unfused_sequence():
+    """The fused step and the four unfused calls give the same gradients (to fp32 summation
+    order) on the same batch; without idx the batch is the first N rows."""
+    import torch
+    M = _mlp()
+    dims, N = (4, 256, 3), 1024
+    rng = np.random.default_rng(15)
+    X = torch.from_numpy(rng.normal(0, 1, (N, 4)).astype(np.float32)).cuda()
+    T = torch.from_numpy(rng.normal(0, 0.3, (N, 3)).astype(np.float32)).cuda()
+    a, b = M.MLP(*dims, max_batch=N, seed=16), M.MLP(*dims, max_batch=N, seed=16)
+    a.train_step_fused(X, T, 1e-3, huber_delta=0.05, grads=True)
+    b.train_step(X, T, 1e-3, huber_delta=0.05)
+    ga, gb = a.grads.cpu().numpy(), b.grads.cpu().numpy()
+    for name, u, w in zip(["W1", "b1", "W2", "b2", "W3", "b3"], OM.split(ga, dims), OM.split(gb, dims)):
+        assert _rel(u, w) < 1e-3, (name, _rel(u, w))
+    assert abs(float(a.loss.item()) - float(b.loss.item())) <= 1e-5 * float(b.loss.item())
+
+
+def test_fused_train_step_rejects_bad_shapes():
+    import ctypes as C
+    import torch
+    M = _mlp()
+    from paper_2606_21784_amd import _lib
+    for dims in ((4, 48, 3), (4, 512, 3), (40, 64, 3)):  # H not a multiple of 32, H > 256, d_in > 32
+        net = M.MLP(*dims, max_batch=16, seed=0)
+        x = torch.zeros((16, dims[0]), dtype=torch.float32, device="cuda")
+        t = torch.zeros((16, dims[2]), dtype=torch.float32, device="cuda")
+        with pytest.raises(_lib.CaeError):
+            net.train_step_fused(x, t, 1e-3)
+    net = M.MLP(4, 32, 3, max_batch=16, seed=0)
+    rc = _lib.lib().cae_mlp_train_step(C.byref(net.net), None, None, None, 4, net.m.data_ptr(), net.v.data_ptr(), 1,
+                                       1e-3, 0.9, 0.999, 1e-8, 0, 0.0, net.loss.data_ptr(), None,
+                                       net.ws.data_ptr(), None)
+    assert rc == _lib.CAE_EINVAL
