@@ -26,46 +26,62 @@ sys.path.insert(0, ROOT)
 
 METRIC = "agent events/s on 1 MI355X + roofline %; surrogate vs exact sweep speedup at ≤5% err"
 
-# --- roofline of the engine kernel (plain integer VALU issue; LDS atomics second) -----------------
+# --- roofline of the engine kernel (plain integer VALU issue; LDS second) ----------------------
 # Peak: 256 CUs x 4 SIMDs x 16 lanes = 64 lane-slots per CU per clock at the 2.4 GHz peak
-# engine clock; a slot is one lane of one full-rate 32-bit VALU instruction.
+# engine clock; a slot is one lane of one full-rate 32-bit VALU instruction (v_add_u32 issues
+# one wave64 instruction per clock per CU when saturated).
 N_CU, LANES_PER_CU, CLOCK_HZ = 256, 64, 2.4e9
 PEAK_SLOTS = N_CU * LANES_PER_CU * CLOCK_HZ  # 3.93e13 slots/s
-# Issue costs in full-rate slots, measured on MI355X by paper_2606_21784_amd/ubench.py in the
-# form the engine issues each instruction (scalar multiplier, zero addend; inside Philox rounds),
-# at 16 waves per CU: the product v_mad_u64_u32 issues at the full rate in the generator's mix,
-# and so do the three-input xor (v_bitop3_b32) and v_mul_hi_u32 with a scalar operand.
-COST = {"mad_u64_u32": 1.0, "mul_hi_u32": 1.0, "alu": 1.0}
-# Algorithmic work per agent event, from the generator and order rules (not from compiled
-# code): Philox4x32-10 with counter (step, agent, market, 0) needs 16 agent-dependent
-# 32x32->64 products and 18 agent-dependent three-input xors (the agent word enters round 1
-# through an xor, so the products of rounds 1-3 that do not depend on it are computed once per
-# market-step: 4 of the 20 products per evaluation); 2 multiply-high range reductions (offset,
-# quantity); 5 ops to form the tick (add, clamp), the side and the book address.  Clearing costs
-# 10 ops per tick per step, i.e. 10 L / A per event.
-PHILOX_PRODUCTS, PHILOX_XORS, RANGE_MULHI, ORDER_OPS, CLEAR_OPS_PER_TICK = 16, 18, 2, 5, 10
-# LDS: one ds_add_u32 per event; the clearing wave reads and writes each tick's (bid, ask) pair
-# once per step (4 words), i.e. 4 L / A lane-words per event.  Sustained ds_add_u32 rate in the
-# engine's aggregation pattern (addresses in a 66-word window), lane-operations per CU per clock,
-# measured by ubench.py at 16 waves per CU.
-LDS_LANE_ATOMICS_PER_CLK_CU = 8.1
+# Issue costs in full-rate slots, measured on MI355X by paper_2606_21784_amd/ubench.py at 16
+# waves per CU (summary keys mad_in_mix_slots, bitop3_slots, mul_hi_slots): the Philox product
+# v_mad_u64_u32 inside Philox rounds (1.14; 1.34 alone), the three-input xor v_bitop3_b32 (1.07)
+# and v_mul_hi_u32 (1.29).
+COST = {"mad_u64_u32": 1.14, "xor3": 1.07, "mul_hi_u32": 1.29, "alu": 1.0}
+# Least VALU work per agent event that this generator and these order rules need, counted from
+# the definitions (not from compiled code):
+#  * Philox4x32-10 with counter (step, agent, market, 0): 20 products and 20 three-input xors,
+#    of which 4 products and 2 xors do not depend on the agent (the agent word enters round 1
+#    through an xor), so they are computed once per market-step: 16 products and 18 xors;
+#  * 2 range reductions (multiply-high for the offset and the quantity; the quantity's +1 rides
+#    in the 64-bit multiply-add's addend);
+#  * 1 op for the order's book word: the side bit and the offset index in one funnel shift
+#    (v_alignbit_b32); the reference price and the clamp to the grid apply per offset bin, not
+#    per agent, when the orders are binned by offset as in the overlapped schedule;
+#  * clearing, per tick and step: the two cumulative sums (2), and per side the unmatched part
+#    max(D - V*, 0) in one saturating subtract and the fill as its difference to the next tick
+#    (2 + 2): 6 ops per tick, i.e. 6 L / A per event.
+PHILOX_PRODUCTS, PHILOX_XORS, RANGE_MULHI, ORDER_OPS, CLEAR_OPS_PER_TICK = 16, 18, 2, 1, 6
+# LDS: one ds_add_u32 per event, at the rate ubench.py measures in the engine's aggregation
+# pattern (addresses in a 66-word window; lds_window_lane_atomics_per_clk_cu), plus the
+# clearing's pass over the book, 4 L / A words per event (read and write each tick's (bid, ask)
+# pair once per step), at the rate of that access form (lds_rw_b64_lane_words_per_clk_cu).
+LDS_LANE_ATOMICS_PER_CLK_CU = 8.2
+LDS_RW_WORDS_PER_CLK_CU = 64.0
 LDS_WORDS_PER_TICK = 4
-PEAK_LDS = N_CU * LDS_LANE_ATOMICS_PER_CLK_CU * CLOCK_HZ
 
 
 def slots_per_event(L, A):
-    return (PHILOX_PRODUCTS * COST["mad_u64_u32"] + PHILOX_XORS * COST["alu"]
+    return (PHILOX_PRODUCTS * COST["mad_u64_u32"] + PHILOX_XORS * COST["xor3"]
             + RANGE_MULHI * COST["mul_hi_u32"] + ORDER_OPS * COST["alu"]
             + CLEAR_OPS_PER_TICK * COST["alu"] * L / A)
 
 
-def lds_ops_per_event(L, A):
-    return 1.0 + LDS_WORDS_PER_TICK * L / A
+def lds_clocks_per_event(L, A):
+    """CU clocks of LDS work per event: the order's atomic and the clearing's share of words."""
+    return 1.0 / LDS_LANE_ATOMICS_PER_CLK_CU + LDS_WORDS_PER_TICK * L / A / LDS_RW_WORDS_PER_CLK_CU
+
+
+def valu_ceiling(L, A):
+    return PEAK_SLOTS / slots_per_event(L, A)
+
+
+def lds_ceiling(L, A):
+    return N_CU * CLOCK_HZ / lds_clocks_per_event(L, A)
 
 
 def ceiling_events_per_s(L, A):
-    """R = min(P_v / w_v, P_l / w_l) for a market of L ticks and A agents."""
-    return min(PEAK_SLOTS / slots_per_event(L, A), PEAK_LDS / lds_ops_per_event(L, A))
+    """R = min(VALU ceiling, LDS ceiling) for a market of L ticks and A agents."""
+    return min(valu_ceiling(L, A), lds_ceiling(L, A))
 
 
 def ensemble_ceiling(descs):
@@ -432,6 +448,10 @@ def main():
                     help="file for every leg's full detail (JSON)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="after timing, copy 1 GiB device-to-device (counter calibration)")
+    ap.add_argument("--steps-per-call", type=int, default=0,
+                    help="auction steps per launch instead of the workload's 1000 (for the HBM "
+                         "check that traffic does not grow with S; the result line then names "
+                         "another workload)")
     args = ap.parse_args()
     VERBOSE = args.verbose
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -447,6 +467,9 @@ def main():
     torch.cuda.set_device(0)
 
     w = workloads.fixed()
+    if args.steps_per_call:
+        w = dict(w, S=args.steps_per_call,
+                 name=w["name"].replace("_S%d" % w["S"], "_S%d" % args.steps_per_call))
     d = w["descs"]
     M, L, A, S = len(d), int(d["L"][0]), int(d["A"][0]), w["S"]
     events = float(np.sum(d["A"].astype(np.float64))) * S
@@ -511,16 +534,16 @@ def main():
         log("copy calibration: 1 GiB read + 1 GiB written")
 
     w_ev = slots_per_event(L, A)
-    w_lds = lds_ops_per_event(L, A)
     rate = events / (kms * 1e-3)  # kernel-time events/s
     achieved = rate * w_ev
-    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12,
+    lds_busy = rate * lds_clocks_per_event(L, A) / (N_CU * CLOCK_HZ)  # fraction of LDS clocks
+    roof = {"bound": "alu" if valu_ceiling(L, A) <= lds_ceiling(L, A) else "lds",
+            "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12,
             "unit": "TOP/s", "frac": achieved / PEAK_SLOTS, "traffic": measured_traffic(),
-            "kernel": "cae_engine_kernel<%d,false,false>" % max(1, L // 64), "kernel_ms": kms,
-            "kernel_ms_last_launch": min(last_ms), "ops_per_event": w_ev,
-            "lds": {"achieved": rate * w_lds / 1e12, "peak": PEAK_LDS / 1e12,
-                    "unit": "T lane-atomics/s", "frac": rate * w_lds / PEAK_LDS,
-                    "ops_per_event": w_lds},
+            "kernel": "cae_engine_kernel<%d,false,false,false>" % max(1, L // 64), "kernel_ms": kms,
+            "kernel_ms_last_launch": min(last_ms), "slots_per_event": round(w_ev, 3),
+            "lds": {"frac": lds_busy, "ceiling_events_per_s": lds_ceiling(L, A),
+                    "clocks_per_event": lds_clocks_per_event(L, A)},
             "ceiling_events_per_s": ceiling_events_per_s(L, A),
             "ceiling_frac": rate / ceiling_events_per_s(L, A)}
 

@@ -86,6 +86,10 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise ImportError("libcae.so is not built (%s); run __graft_entry__.build() or "
                           "python paper_2606_21784_amd/build.py" % LIB_PATH)
+    # torch ships its own HIP runtime.  Loaded first, it is the one libcae.so binds to, so the
+    # library's calls see the same devices, memory and streams as torch's tensors; loading
+    # libcae.so first would map the system runtime as a second copy that torch does not use.
+    import torch  # noqa: F401
     L = C.CDLL(LIB_PATH)
     P, u32, u64, i32 = C.c_void_p, C.c_uint32, C.c_uint64, C.c_int
     L.cae_strerror.argtypes = [i32]

@@ -38,6 +38,7 @@ enum Kind : int {
     K_MAD_U64_CONST = 10,
     K_PHILOX_ROUNDS = 11,
     K_GEN_NOISE = 12,
+    K_LDS_RW_B64 = 13,
 };
 
 // Shader-clock cycles and 100 MHz real-time ticks of the timed loop, per workgroup.
@@ -137,6 +138,39 @@ __global__ void __launch_bounds__(1024) ub_lds(uint32_t *out, uint64_t *clk, uin
         clk[2 * blockIdx.x + 1] = r1 - r0;
     }
     out[blockIdx.x * blockDim.x + threadIdx.x] = buf[wave][lane];
+}
+
+// The clearing's LDS traffic: each lane reads a (bid, ask) pair with ds_read_b64, adds to both
+// words and writes the pair back with ds_write_b64; four independent pairs per lane (lane l of a
+// wave owns pairs l, 64 + l, 128 + l, 192 + l of the wave's own region, so a wave's accesses
+// cover consecutive 8-byte slots without bank conflicts).  16 lane-words moved per iteration.
+__global__ void __launch_bounds__(1024) ub_lds_rw(uint32_t *out, uint64_t *clk, uint32_t iters, uint32_t seed)
+{
+    __shared__ uint2 pairs[16][256];
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+    for (uint32_t i = threadIdx.x; i < 16 * 256; i += blockDim.x) (&pairs[0][0])[i] = make_uint2(0u, 0u);
+    __syncthreads();
+    uint64_t c0, r0, c1, r1;
+    stamp(clk, c0, r0);
+    for (uint32_t i = 0; i < iters; ++i) {
+        uint2 v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[j] = pairs[wave][64u * j + lane];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            v[j].x += seed;
+            v[j].y += i;
+            pairs[wave][64u * j + lane] = v[j];
+        }
+    }
+    __syncthreads();
+    stamp(clk, c1, r1);
+    if (threadIdx.x == 0) {
+        clk[2 * blockIdx.x] = c1 - c0;
+        clk[2 * blockIdx.x + 1] = r1 - r0;
+    }
+    const uint2 a = pairs[wave][lane], b = pairs[wave][192u + lane];
+    out[blockIdx.x * blockDim.x + threadIdx.x] = a.x ^ a.y ^ b.x ^ b.y;
 }
 
 // 8 chains of v_mad_u64_u32 with a uniform multiplier and no addend; the high word feeds the
@@ -258,7 +292,8 @@ extern "C" {
 
 // Runs one microbenchmark: `blocks` workgroups of `threads` threads (64..1024), `iters` iterations
 // (8 operations per lane for the single-instruction kinds; 80 instructions per lane for
-// philox_rounds; 128 agent events per wave for gen_noise, whose iters must be a multiple of 8).  Writes the elapsed milliseconds to *ms and, per workgroup, the shader
+// philox_rounds; 16 LDS words read or written per lane for lds_rw_b64; 128 agent events per wave
+// for gen_noise, whose iters must be a multiple of 8).  Writes the elapsed milliseconds to *ms and, per workgroup, the shader
 // clock cycles and 100 MHz real-time ticks of its timed loop to clk[2*b], clk[2*b+1].  out must
 // hold blocks*threads words and clk 2*blocks 64-bit words of device memory.  Returns 0, or -1 for
 // an unknown kind, -4 for a HIP error.
@@ -282,6 +317,7 @@ int cae_ubench_run(int kind, uint32_t blocks, uint32_t threads, uint32_t iters, 
     case K_LDS_ADD_WINDOW: hipLaunchKernelGGL(ub_lds<K_LDS_ADD_WINDOW>, g, b, 0, nullptr, out, clk, iters, 1u); break;
     case K_FMA_F32: hipLaunchKernelGGL(ub_valu<K_FMA_F32>, g, b, 0, nullptr, out, clk, iters, 1u); break;
     case K_FMA_F64: hipLaunchKernelGGL(ub_valu<K_FMA_F64>, g, b, 0, nullptr, out, clk, iters, 1u); break;
+    case K_LDS_RW_B64: hipLaunchKernelGGL(ub_lds_rw, g, b, 0, nullptr, out, clk, iters, 1u); break;
     case K_MAD_U64_CONST: hipLaunchKernelGGL(ub_mad_const, g, b, 0, nullptr, out, clk, iters, kM0); break;
     case K_PHILOX_ROUNDS: hipLaunchKernelGGL(ub_philox_rounds, g, b, 0, nullptr, out, clk, iters, 1u, 2u); break;
     case K_GEN_NOISE:

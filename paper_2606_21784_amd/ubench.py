@@ -25,10 +25,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 KINDS = {"v_add_u32": 0, "v_xor_b32": 1, "v_bitop3_b32": 2, "v_mul_hi_u32": 3,
          "v_mul_lo_u32": 4, "v_mad_u64_u32": 5, "ds_add_u32_conflict_free": 6,
          "ds_add_u32_window66": 7, "v_fma_f32": 8, "v_fma_f64": 9,
-         "mad_u64_const": 10, "philox_rounds": 11, "gen_noise_events": 12}
+         "mad_u64_const": 10, "philox_rounds": 11, "gen_noise_events": 12, "ds_rw_b64_words": 13}
 # operations per lane and loop iteration of each kernel
 OPS_PER_ITER = {k: 8 for k in KINDS}
-OPS_PER_ITER.update({"philox_rounds": 80, "gen_noise_events": 2})
+OPS_PER_ITER.update({"philox_rounds": 80, "gen_noise_events": 2, "ds_rw_b64_words": 16})
 
 
 def measure(iters=4096, reps=3):
@@ -50,7 +50,7 @@ def measure(iters=4096, reps=3):
             for _ in range(reps):
                 ms = C.c_float()
                 it = iters // 4 if name.startswith("ds_") else iters
-                if OPS_PER_ITER[name] != 8:  # ~80 instructions per iteration (a multiple of 8)
+                if name in ("philox_rounds", "gen_noise_events"):  # ~80 instructions per iteration
                     it = max(8, iters // 8)
                 rc = lib.cae_ubench_run(k, blocks, threads, it, out.data_ptr(), clk.data_ptr(),
                                         C.byref(ms))
@@ -81,7 +81,9 @@ def summary(res, nw=16):
                            (generator, range reductions, clamp, book word);
       gen_events_per_clk_cu: its agent events per clock per CU;
       lds_window_lane_atomics_per_clk_cu: ds_add_u32 lane-operations per clock per CU in a
-                           66-word window (the engine's aggregation pattern)."""
+                           66-word window (the engine's aggregation pattern);
+      lds_rw_b64_lane_words_per_clk_cu: 32-bit words per clock per CU moved by the clearing's
+                           access form (ds_read_b64 and ds_write_b64 of (bid, ask) pairs)."""
     g = lambda k: res["%s@%dw" % (k, nw)]["cu_ipc"]
     full = g("v_add_u32")
     xor3 = full / g("v_bitop3_b32")
@@ -96,6 +98,7 @@ def summary(res, nw=16):
            "gen_slots_per_event": 64.0 * full / (64.0 * g("gen_noise_events")),
            "lds_window_lane_atomics_per_clk_cu": 64.0 * g("ds_add_u32_window66"),
            "lds_conflict_free_lane_atomics_per_clk_cu": 64.0 * g("ds_add_u32_conflict_free"),
+           "lds_rw_b64_lane_words_per_clk_cu": 64.0 * g("ds_rw_b64_words"),
            "ghz": res["v_add_u32@%dw" % nw]["ghz"]}
     return out
 
