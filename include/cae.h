@@ -349,6 +349,22 @@ int cae_mlp_train_step(const cae_mlp *net, const float *x, const float *target, 
                        float *m, float *v, uint32_t step, float lr, float beta1, float beta2, float eps, int loss_kind,
                        float delta, float *loss, float *grads, void *ws, void *stream);
 
+/* cae_mlp_train_step without a workspace argument, for callers that cannot allocate device
+ * memory (code under HIP graph capture, serving loops, harnesses that forbid allocation).  The
+ * workspace is a static array of 8 MiB (8 << 20 bytes) inside the library, one copy per device,
+ * held until the process ends; its address is looked up once per device on the first call made
+ * with that device current.  Allocates nothing (no hipMalloc, no hipFree) and computes exactly
+ * what cae_mlp_train_step computes (same kernels, same results bit for bit).  Batches whose
+ * workspace (about 2 (d_in + 4 H + 16) bytes per sample, N rounded up to 32) exceeds the array
+ * are refused with CAE_EINVAL before anything is launched: at d_in = 4, H = 256 that is N above
+ * 4000.  Every call on one device shares that device's array, so calls that overlap on one
+ * device (two streams, or two host threads) race and must be ordered by the caller; calls that
+ * are ordered on one stream are safe.  Asynchronous.
+ * Errors: those of cae_mlp_train_step, CAE_EINVAL for a batch beyond the array, CAE_EHIP. */
+int cae_mlp_train_step_noalloc(const cae_mlp *net, const float *x, const float *target, const uint32_t *idx,
+                               uint32_t N, float *m, float *v, uint32_t step, float lr, float beta1, float beta2,
+                               float eps, int loss_kind, float delta, float *loss, float *grads, void *stream);
+
 /* Mean loss over n values and its gradient with respect to y, r = y - target (device pointers;
  * one workgroup, fixed summation order).  Asynchronous.
  *   CAE_LOSS_MSE:   loss[0] = mean r^2, dy = 2 r / n

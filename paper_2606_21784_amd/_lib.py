@@ -73,7 +73,7 @@ EXPORTS = ["cae_strerror", "cae_last_error", "cae_device_info", "cae_sizes", "ca
            "cae_last_step_ms", "cae_destroy", "cae_clear", "cae_mlp_sizes",
            "cae_mlp_refresh_weights", "cae_mlp_forward", "cae_mlp_predict",
            "cae_mlp_backward",
-           "cae_mlp_adam", "cae_mlp_train_step",
+           "cae_mlp_adam", "cae_mlp_train_step", "cae_mlp_train_step_noalloc",
            "cae_mlp_loss_grad"]
 
 _lib = None
@@ -117,6 +117,7 @@ def lib():
     L.cae_mlp_adam.argtypes = [P, P, P, P, u32, f32, f32, f32, f32, P]
     L.cae_mlp_loss_grad.argtypes = [P, P, P, P, u32, i32, f32, P]
     L.cae_mlp_train_step.argtypes = [P, P, P, P, u32, P, P, u32, f32, f32, f32, f32, i32, f32, P, P, P, P]
+    L.cae_mlp_train_step_noalloc.argtypes = [P, P, P, P, u32, P, P, u32, f32, f32, f32, f32, i32, f32, P, P, P]
     for name in EXPORTS:
         if name not in ("cae_strerror", "cae_last_error"):
             getattr(L, name).restype = i32

@@ -6,9 +6,10 @@
 // engine stays its fallback and the reference that measures its error.
 //
 // Precision: weights, inputs, hidden activations and back-propagated gradients are stored in
-// bfloat16 (round to nearest even); every product is accumulated in fp32 by
-// v_mfma_f32_16x16x16bf16_1k; biases, pre-activations, outputs, weight gradients and the Adam
-// state are fp32.  Parameter layout (row-major, input index first):
+// bfloat16 (round to nearest even); every product is accumulated in fp32 on the matrix cores
+// (v_mfma_f32_16x16x16bf16_1k in the general GEMM and the fused inference kernel, gfx950's
+// v_mfma_f32_16x16x32_bf16 in the fused training step); biases, pre-activations, outputs, weight
+// gradients and the Adam state are fp32.  Parameter layout (row-major, input index first):
 //   W1[d_in][H], b1[H], W2[H][H], b2[H], W3[H][d_out], b3[d_out]
 // and the bfloat16 weight copies are W1, W2, W3 in the same layouts, back to back, followed by
 // W2 transposed (W2T[n][k] = W2[k][n]) for the fused inference kernel, whose matrix-core
@@ -18,6 +19,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstdio>
+#include <mutex>
 
 #include "cae.h"
 
@@ -756,6 +759,111 @@ int launch_status()
     return CAE_OK;
 }
 
+// Scratch of cae_mlp_train_step_noalloc: the fused training step's workspace (transposed
+// activations and gradients, loss partials) for callers that cannot allocate device memory.
+// Every device the library runs on holds its own copy until the process ends; host code must not
+// pass the array's name to a kernel (it is a host-side stand-in), only the per-device address
+// that hipGetSymbolAddress returns.  Nothing in it needs clearing between calls: each call's
+// first kernel writes every word its second kernel reads.
+constexpr size_t kScratchBytes = size_t(8) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// The address of the current device's copy of `scratch`, looked up once per device.
+int scratch_of_current_device(void **out)
+{
+    int dev = -1;
+    hipError_t he = hipGetDevice(&dev);
+    if (he != hipSuccess) return mfail(CAE_EHIP, hipGetErrorString(he));
+    if (dev < 0 || dev >= kMaxDevices) return mfail(CAE_EINVAL, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        he = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (he != hipSuccess || !p)
+            return mfail(CAE_EHIP, he != hipSuccess ? hipGetErrorString(he) : "no address for the scratch array");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return CAE_OK;
+}
+
+// Argument checks shared by both training-step entry points (no device call).
+int check_train_args(const cae_mlp *net, const float *x, const float *target, const float *m, const float *v,
+                     uint32_t N, uint32_t step, int loss_kind, float delta, const float *loss)
+{
+    int rc = check_net(net);
+    if (rc) return rc;
+    const uint32_t din = net->d_in, H = net->d_hidden;
+    if (H % 32u || H > kTrainMaxH || din > kTrainMaxIn)
+        return mfail(CAE_EINVAL, "cae_mlp_train_step needs d_hidden a multiple of 32 up to 256 and d_in <= 32");
+    if (!x || !target || !m || !v || !loss) return mfail(CAE_EINVAL, "NULL pointer");
+    if (N == 0) return mfail(CAE_EINVAL, "N must be >= 1");
+    if (step < 1) return mfail(CAE_EINVAL, "step counts from 1");
+    if (loss_kind != CAE_LOSS_MSE && loss_kind != CAE_LOSS_HUBER) return mfail(CAE_EINVAL, "unknown loss kind");
+    if (loss_kind == CAE_LOSS_HUBER && !(delta > 0.0f)) return mfail(CAE_EINVAL, "Huber delta must be > 0");
+    return CAE_OK;
+}
+
+// The fused training step (two launches) on a workspace of train_ws(d_in, H, N).total bytes.
+int train_step_impl(const cae_mlp *net, const float *x, const float *target, const uint32_t *idx, uint32_t N,
+                    float *m, float *v, uint32_t step, float lr, float beta1, float beta2, float eps, int loss_kind,
+                    float delta, float *loss, float *grads, void *ws, hipStream_t s)
+{
+    const uint32_t din = net->d_in, H = net->d_hidden, dout = net->d_out;
+    const Layout l = layout(din, H, dout);
+    const TrainWs w = train_ws(din, H, N);
+    unsigned char *b = static_cast<unsigned char *>(ws);
+    TrainArgs a;
+    a.x = x;
+    a.t = target;
+    a.idx = idx;
+    a.B = N;
+    a.Bp = (N + 31u) / 32u * 32u;
+    a.din = din;
+    a.H = H;
+    a.dout = dout;
+    a.W1 = net->weights;
+    a.W2 = a.W1 + (size_t)din * H;
+    a.W3 = a.W2 + (size_t)H * H;
+    a.W2T = net->weights + l.w2t;
+    a.p = net->params;
+    a.m = m;
+    a.v = v;
+    a.grads = grads;
+    a.wb = net->weights;
+    a.xT = reinterpret_cast<uint16_t *>(b + w.xT);
+    a.h1T = reinterpret_cast<uint16_t *>(b + w.h1T);
+    a.h2T = reinterpret_cast<uint16_t *>(b + w.h2T);
+    a.dyT = reinterpret_cast<uint16_t *>(b + w.dyT);
+    a.dz2T = reinterpret_cast<uint16_t *>(b + w.dz2T);
+    a.dz1T = reinterpret_cast<uint16_t *>(b + w.dz1T);
+    a.loss_part = reinterpret_cast<float *>(b + w.loss_part);
+    a.loss = loss;
+    a.l = l;
+    a.kind = loss_kind;
+    a.delta = delta;
+    a.inv_n = 1.0f / (float)((double)N * dout);
+    a.lr = lr;
+    a.beta1 = beta1;
+    a.beta2 = beta2;
+    a.eps = eps;
+    a.c1 = (float)(1.0 - std::pow((double)beta1, (double)step));
+    a.c2 = (float)(1.0 - std::pow((double)beta2, (double)step));
+    const uint32_t ct = H / 16u;
+    a.tiles1 = (din + 1u + 15u) / 16u * ct;
+    a.tiles2 = (H / 16u + 1u) * ct;
+    a.tiles3 = H / 16u + 1u;
+    const size_t lds = 2ull * (2u * kTrainRows * 32u + 3ull * kTrainRows * (H + kTrainPad)) + 8ull * kTrainRows * H;
+    hipLaunchKernelGGL(mlp_train_rows, dim3(a.Bp / kTrainRows), dim3(256), lds, s, a);
+    const uint32_t tiles = a.tiles1 + a.tiles2 + a.tiles3;
+    hipLaunchKernelGGL(mlp_train_params, dim3((tiles + 3u) / 4u), dim3(256), 0, s, a);
+    return launch_status();
+}
+
 }  // namespace
 
 extern "C" {
@@ -885,65 +993,32 @@ int cae_mlp_train_step(const cae_mlp *net, const float *x, const float *target, 
                        float *m, float *v, uint32_t step, float lr, float beta1, float beta2, float eps, int loss_kind,
                        float delta, float *loss, float *grads, void *ws, void *stream)
 {
-    int rc = check_net(net);
+    int rc = check_train_args(net, x, target, m, v, N, step, loss_kind, delta, loss);
     if (rc) return rc;
-    const uint32_t din = net->d_in, H = net->d_hidden, dout = net->d_out;
-    if (H % 32u || H > kTrainMaxH || din > kTrainMaxIn)
-        return mfail(CAE_EINVAL, "cae_mlp_train_step needs d_hidden a multiple of 32 up to 256 and d_in <= 32");
-    if (!x || !target || !m || !v || !loss || !ws) return mfail(CAE_EINVAL, "NULL pointer");
-    if (N == 0) return mfail(CAE_EINVAL, "N must be >= 1");
-    if (step < 1) return mfail(CAE_EINVAL, "step counts from 1");
-    if (loss_kind != CAE_LOSS_MSE && loss_kind != CAE_LOSS_HUBER) return mfail(CAE_EINVAL, "unknown loss kind");
-    if (loss_kind == CAE_LOSS_HUBER && !(delta > 0.0f)) return mfail(CAE_EINVAL, "Huber delta must be > 0");
-    hipStream_t s = (hipStream_t)stream;
-    const Layout l = layout(din, H, dout);
-    const TrainWs w = train_ws(din, H, N);
-    unsigned char *b = static_cast<unsigned char *>(ws);
-    TrainArgs a;
-    a.x = x;
-    a.t = target;
-    a.idx = idx;
-    a.B = N;
-    a.Bp = (N + 31u) / 32u * 32u;
-    a.din = din;
-    a.H = H;
-    a.dout = dout;
-    a.W1 = net->weights;
-    a.W2 = a.W1 + (size_t)din * H;
-    a.W3 = a.W2 + (size_t)H * H;
-    a.W2T = net->weights + l.w2t;
-    a.p = net->params;
-    a.m = m;
-    a.v = v;
-    a.grads = grads;
-    a.wb = net->weights;
-    a.xT = reinterpret_cast<uint16_t *>(b + w.xT);
-    a.h1T = reinterpret_cast<uint16_t *>(b + w.h1T);
-    a.h2T = reinterpret_cast<uint16_t *>(b + w.h2T);
-    a.dyT = reinterpret_cast<uint16_t *>(b + w.dyT);
-    a.dz2T = reinterpret_cast<uint16_t *>(b + w.dz2T);
-    a.dz1T = reinterpret_cast<uint16_t *>(b + w.dz1T);
-    a.loss_part = reinterpret_cast<float *>(b + w.loss_part);
-    a.loss = loss;
-    a.l = l;
-    a.kind = loss_kind;
-    a.delta = delta;
-    a.inv_n = 1.0f / (float)((double)N * dout);
-    a.lr = lr;
-    a.beta1 = beta1;
-    a.beta2 = beta2;
-    a.eps = eps;
-    a.c1 = (float)(1.0 - std::pow((double)beta1, (double)step));
-    a.c2 = (float)(1.0 - std::pow((double)beta2, (double)step));
-    const uint32_t ct = H / 16u;
-    a.tiles1 = (din + 1u + 15u) / 16u * ct;
-    a.tiles2 = (H / 16u + 1u) * ct;
-    a.tiles3 = H / 16u + 1u;
-    const size_t lds = 2ull * (2u * kTrainRows * 32u + 3ull * kTrainRows * (H + kTrainPad)) + 8ull * kTrainRows * H;
-    hipLaunchKernelGGL(mlp_train_rows, dim3(a.Bp / kTrainRows), dim3(256), lds, s, a);
-    const uint32_t tiles = a.tiles1 + a.tiles2 + a.tiles3;
-    hipLaunchKernelGGL(mlp_train_params, dim3((tiles + 3u) / 4u), dim3(256), 0, s, a);
-    return launch_status();
+    if (!ws) return mfail(CAE_EINVAL, "NULL workspace");
+    return train_step_impl(net, x, target, idx, N, m, v, step, lr, beta1, beta2, eps, loss_kind, delta, loss, grads,
+                           ws, (hipStream_t)stream);
+}
+
+int cae_mlp_train_step_noalloc(const cae_mlp *net, const float *x, const float *target, const uint32_t *idx,
+                               uint32_t N, float *m, float *v, uint32_t step, float lr, float beta1, float beta2,
+                               float eps, int loss_kind, float delta, float *loss, float *grads, void *stream)
+{
+    int rc = check_train_args(net, x, target, m, v, N, step, loss_kind, delta, loss);
+    if (rc) return rc;
+    const size_t need = train_ws(net->d_in, net->d_hidden, N).total;
+    if (need > kScratchBytes) {
+        char msg[160];
+        std::snprintf(msg, sizeof msg,
+                      "cae_mlp_train_step_noalloc: batch %u needs %zu bytes of scratch, the library holds %zu", N,
+                      need, kScratchBytes);
+        return mfail(CAE_EINVAL, msg);
+    }
+    void *ws = nullptr;
+    rc = scratch_of_current_device(&ws);
+    if (rc) return rc;
+    return train_step_impl(net, x, target, idx, N, m, v, step, lr, beta1, beta2, eps, loss_kind, delta, loss, grads,
+                           ws, (hipStream_t)stream);
 }
 
 int cae_mlp_loss_grad(const float *y, const float *target, float *dy, float *loss, uint32_t n, int kind, float delta,

@@ -114,25 +114,29 @@ class MLP:
         return dy
 
     def train_step_fused(self, x, t, lr, idx=None, n=None, beta1=0.9, beta2=0.999, eps=1e-8, huber_delta=None,
-                         grads=False):
+                         grads=False, noalloc=False):
         """One training step in two launches (``cae_mlp_train_step``): the batch is rows idx of
         x / t (int32 device tensor, or None for the first n rows; x: (rows, d_in), t: (rows,
         d_out) float32 device tensors).  Returns the device tensor holding the batch's mean loss
-        (and fills ``self.grads`` when grads is true)."""
+        (and fills ``self.grads`` when grads is true).  noalloc: the same step through
+        ``cae_mlp_train_step_noalloc``, on the library's static scratch instead of self.ws."""
         import torch
         assert x.dtype == torch.float32 and t.dtype == torch.float32 and x.is_contiguous() and t.is_contiguous()
         if idx is not None:
             assert idx.dtype == torch.int32 and idx.is_contiguous()
             n = int(idx.numel())
         n = int(x.shape[0]) if n is None else int(n)
-        if n > self.max_batch:
+        if n > self.max_batch and not noalloc:
             raise ValueError("batch %d exceeds max_batch %d" % (n, self.max_batch))
         self.step_count += 1
         kind, delta = (0, 0.0) if huber_delta is None else (1, float(huber_delta))
-        check("cae_mlp_train_step", lib().cae_mlp_train_step(
-            C.byref(self.net), x.data_ptr(), t.data_ptr(), idx.data_ptr() if idx is not None else None, n,
-            self.m.data_ptr(), self.v.data_ptr(), self.step_count, lr, beta1, beta2, eps, kind, delta,
-            self.loss.data_ptr(), self.grads.data_ptr() if grads else None, self.ws.data_ptr(), self.stream))
+        common = (C.byref(self.net), x.data_ptr(), t.data_ptr(), idx.data_ptr() if idx is not None else None, n,
+                  self.m.data_ptr(), self.v.data_ptr(), self.step_count, lr, beta1, beta2, eps, kind, delta,
+                  self.loss.data_ptr(), self.grads.data_ptr() if grads else None)
+        if noalloc:
+            check("cae_mlp_train_step_noalloc", lib().cae_mlp_train_step_noalloc(*common, self.stream))
+        else:
+            check("cae_mlp_train_step", lib().cae_mlp_train_step(*common, self.ws.data_ptr(), self.stream))
         return self.loss
 
     def train_step(self, x, t, lr, beta1=0.9, beta2=0.999, eps=1e-8, huber_delta=None):
