@@ -56,7 +56,7 @@ PHILOX_PRODUCTS, PHILOX_XORS, RANGE_MULHI, ORDER_OPS, CLEAR_OPS_PER_TICK = 16, 1
 # clearing's pass over the book, 4 L / A words per event (read and write each tick's (bid, ask)
 # pair once per step), at the rate of that access form (lds_rw_b64_lane_words_per_clk_cu).
 LDS_LANE_ATOMICS_PER_CLK_CU = 8.2
-LDS_RW_WORDS_PER_CLK_CU = 64.0
+LDS_RW_WORDS_PER_CLK_CU = 107.7
 LDS_WORDS_PER_TICK = 4
 
 
