@@ -166,8 +166,10 @@ typedef struct cae_tuning {
                                                    orders (rows of 64/P agents) and for the
                                                    clearing (one book per lane segment);
                                                    0 = off.  Applies to last-tick Philox
-                                                   markets with L <= 256/P (others of the
-                                                   class run unpacked); the class then runs
+                                                   markets with L <= 512/P (up to 8 ticks
+                                                   per lane of a segment) in ensembles whose
+                                                   books all have at most 128 ticks (others
+                                                   of the class run unpacked); the class runs
                                                    one wave per P markets (waves_per_market,
                                                    pipelined and overlap are ignored).     */
 } cae_tuning;

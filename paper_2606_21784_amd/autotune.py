@@ -9,7 +9,7 @@ The engine's schedule has these knobs (``cae_tuning`` in include/cae.h):
     generate the next step's orders while one wave clears, the clearing wave taking overlap - 1
     rows of 64 agents after its clearing;
   * pack, per size class (small last-tick markets in an ensemble of books of at most 128
-    ticks): P = 2 or 4 markets share one wave, 64 / P lanes each;
+    ticks): P = 2 or 4 markets share one wave, 64 / P lanes each (up to 8 ticks per lane);
   * waves per workgroup: how many markets of one class share a workgroup (in lock-step when a
     market spans more than one wave) and therefore how the workgroup's LDS is partitioned into
     market slices;
@@ -128,7 +128,7 @@ def tune(descs, seed=0, S_probe=None, min_markets=None, cache=None, arch="gfx950
         # packed candidates first (the narrowest schedules): small last-tick Philox markets
         packable = (small_books and int(probe["flags"].max()) == 0)
         cands = [(1, False, G, 0, P) for P in PACK_CANDIDATES for G in (4, 8)
-                 if packable and int(probe["L"].max()) <= 256 // P]
+                 if packable and int(probe["L"].max()) <= 512 // P]
         cands += [(w, False, max(4, w), 0, 0) for w in WPM_CANDIDATES] + [(1, True, G, 0, 0) for G in PIPE_GROUPS]
         best = None
         timings = []

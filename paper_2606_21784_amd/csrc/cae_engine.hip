@@ -841,9 +841,24 @@ __device__ __forceinline__ void run_market(const EngineArgs &args, const Item &i
     if constexpr (FULL && MULTI) __syncthreads();  // every wave has read the book before orders land
 
     const double *lnT = args.lnT + d.L;  // ln(L + tick)
+    // The log return of step i is added after step i + 1's orders are generated, so the table
+    // load issued after the clearing has long returned when it is used (same values, same order
+    // of the floating-point sums).  ln_last = ln(L + last) of the step before.
+    double ln_last = 0.0, ln_new = 0.0;
+    if constexpr (!kLazy) {
+        if (active) ln_last = lnT[last];
+    }
     for (uint32_t i = 0; i < args.S; ++i) {
         const uint32_t s = (uint32_t)steps0 + i;
         if (active) gen_orders<FULL>(d, d.id, s, Refs{last, prev, mid2, mid2p}, args.k0, args.k1, t, nthr, bk);
+        if constexpr (!kLazy) {
+            if (active && i >= 1u) {
+                const double r = ln_new - ln_last;
+                sum_r = sum_r + r;
+                sum_r2 = sum_r2 + r * r;
+                ln_last = ln_new;
+            }
+        }
         if constexpr (MULTI) __syncthreads();
         else wave_sync();
         ClearOut co;
@@ -883,15 +898,20 @@ __device__ __forceinline__ void run_market(const EngineArgs &args, const Item &i
                     sum_spread += (uint64_t)(co.ba - co.bb);
                     n_spread += 1;
                 }
-                const double r = lnT[last] - lnT[prev];
-                sum_r = sum_r + r;
-                sum_r2 = sum_r2 + r * r;
+                ln_new = lnT[last];  // this step's return is added during the next step
             }
             mid2p = mid2;
             mid2 = next_mid2(mid, co.bb, co.ba, last);
             if constexpr (TRACE) {
                 if (t == 0) trace_step(args, m, i, last, co.v);
             }
+        }
+    }
+    if constexpr (!kLazy) {
+        if (active && args.S >= 1u) {  // the last step's log return
+            const double r = ln_new - ln_last;
+            sum_r = sum_r + r;
+            sum_r2 = sum_r2 + r * r;
         }
     }
     if constexpr (kLazy) {
@@ -1506,7 +1526,6 @@ __device__ __forceinline__ uint32_t seg_crossing_lane(bool pred, uint32_t base)
 template <int TPL, int SEGLOG>
 __device__ __forceinline__ ClearOut clear_seg(uint32_t *__restrict__ bk, uint32_t ll, uint32_t base, bool wr)
 {
-    constexpr uint32_t kSeg = 1u << SEGLOG;
     const uint32_t q0 = ll * TPL;
     uint32_t b[TPL], k[TPL];
     load_pairs<TPL>(bk, q0, b, k);
@@ -1518,6 +1537,7 @@ __device__ __forceinline__ ClearOut clear_seg(uint32_t *__restrict__ bk, uint32_
     }
     uint32_t ib = sb, ia = sa;
     seg_scan_add2<SEGLOG>(ib, ia);
+    constexpr uint32_t kSeg = 1u << SEGLOG;
     const uint32_t Tb = lane_value(ib, base + kSeg - 1u);
     uint32_t D[TPL + 1], Sq[TPL];
     D[0] = Tb - (ib - sb);
@@ -1565,10 +1585,84 @@ __device__ __forceinline__ ClearOut clear_seg(uint32_t *__restrict__ bk, uint32_
     return out;
 }
 
+// clear_seg for books of 8 ticks per lane: the same passes, with the demand and supply of each
+// tick re-formed by running sums in every pass instead of held in arrays, so that only the 16
+// book words stay live (the packed kernels run at their register limit).
+template <int TPL, int SEGLOG>
+__device__ __forceinline__ ClearOut clear_seg_lean(uint32_t *__restrict__ bk, uint32_t ll, uint32_t base, bool wr)
+{
+    const uint32_t q0 = ll * TPL;
+    uint32_t b[TPL], k[TPL];
+    load_pairs<TPL>(bk, q0, b, k);
+    uint32_t sb = 0, sa = 0;
+#pragma unroll
+    for (int j = 0; j < TPL; ++j) {
+        sb += b[j];
+        sa += k[j];
+    }
+    uint32_t ib = sb, ia = sa;
+    seg_scan_add2<SEGLOG>(ib, ia);
+    constexpr uint32_t kSeg = 1u << SEGLOG;
+    const uint32_t Tb = lane_value(ib, base + kSeg - 1u);
+    const uint32_t D0 = Tb - (ib - sb);  // demand at the lane's first tick
+    const uint32_t Sb = ia - sa;         // asks below the lane's first tick
+    uint32_t vc = Sb, d = D0, sq = Sb;
+#pragma unroll
+    for (int j = 0; j < TPL; ++j) {
+        sq += k[j];
+        vc = max(vc, min(d, sq));
+        d -= b[j];
+    }
+    // sq = S of the lane's top tick (= ia), d + b[TPL - 1] = D of that tick
+    ClearOut out;
+    out.v = lane_value(vc, seg_crossing_lane<SEGLOG>(ia >= d + b[TPL - 1], base));
+    const uint32_t vs = out.v;
+    {
+        uint32_t pj = q0, t = Sb;
+#pragma unroll
+        for (int j = 0; j < TPL; ++j) {
+            t += k[j];
+            pj += t < vs ? 1u : 0u;
+        }
+        out.p = lane_value(pj, seg_crossing_lane<SEGLOG>(ia >= vs, base));
+    }
+    uint32_t md = min(D0, vs), ms = min(Sb, vs);
+    d = D0;
+    sq = Sb;
+#pragma unroll
+    for (int j = 0; j < TPL; ++j) {
+        d -= b[j];
+        sq += k[j];
+        const uint32_t md1 = min(d, vs), ms1 = min(sq, vs);
+        b[j] -= md - md1;
+        k[j] -= ms1 - ms;
+        md = md1;
+        ms = ms1;
+    }
+    if (wr) store_pairs<TPL>(bk, q0, b, k);
+    uint32_t hb = kNone, la = kNone;
+#pragma unroll
+    for (int j = 0; j < TPL; ++j)
+        if (b[j] != 0) hb = q0 + j;
+#pragma unroll
+    for (int j = TPL - 1; j >= 0; --j)
+        if (k[j] != 0) la = q0 + j;
+    const uint32_t mb = seg_bits<SEGLOG>(ballot(hb != kNone), base);
+    const uint32_t ma = seg_bits<SEGLOG>(ballot(la != kNone), base);
+    const uint32_t bbv = lane_value(hb, base + (mb ? 31u - (uint32_t)__builtin_clz(mb) : 0u));
+    const uint32_t bav = lane_value(la, base + (ma ? (uint32_t)__builtin_ctz(ma) : 0u));
+    out.bb = mb ? bbv : kNone;
+    out.ba = ma ? bav : kNone;
+    return out;
+}
+
 template <int SEGLOG>
 __device__ __forceinline__ ClearOut clear_seg_dispatch(uint32_t *bk, uint32_t tpl, uint32_t ll, uint32_t base,
                                                        bool wr)
 {
+    if constexpr (SEGLOG == 4) {  // 16-lane segments hold books of up to 128 ticks
+        if (tpl >= 8u) return clear_seg_lean<8, SEGLOG>(bk, ll, base, wr);
+    }
     if (tpl >= 4u) return clear_seg<4, SEGLOG>(bk, ll, base, wr);
     if (tpl == 2u) return clear_seg<2, SEGLOG>(bk, ll, base, wr);
     return clear_seg<1, SEGLOG>(bk, ll, base, wr);
@@ -1617,6 +1711,9 @@ __device__ __forceinline__ void run_packed_seg(const EngineArgs &args, const Ite
     wave_sync();
     const double *lnT = args.lnT + d.L;  // ln(L + tick)
     const uint32_t A = active ? d.A : 0u;
+    // each step's log return is added after the next step's orders (the table load is then long
+    // back); ln_last = ln(L + last) of the step before
+    double ln_last = active ? lnT[last] : 0.0, ln_new = 0.0;
     for (uint32_t i = 0; i < args.S; ++i) {
         const uint32_t s = s0 + i;
         {
@@ -1636,6 +1733,12 @@ __device__ __forceinline__ void run_packed_seg(const EngineArgs &args, const Ite
                 }
             }
         }
+        if (active && i >= 1u) {
+            const double r = ln_new - ln_last;
+            sum_r = sum_r + r;
+            sum_r2 = sum_r2 + r * r;
+            ln_last = ln_new;
+        }
         wave_sync();
         // a segment without a market reads slot 0's book (its lanes point there) but writes
         // nothing
@@ -1654,14 +1757,17 @@ __device__ __forceinline__ void run_packed_seg(const EngineArgs &args, const Ite
                     atomicAdd(reinterpret_cast<unsigned long long *>(acc + 4), 1ull);
                 }
             }
-            const double r = lnT[last] - lnT[prev];
-            sum_r = sum_r + r;
-            sum_r2 = sum_r2 + r * r;
+            ln_new = lnT[last];
             if constexpr (TRACE) {
                 if (ll == 0) trace_step(args, m, i, last, co.v);
             }
         }
         wave_sync();
+    }
+    if (active && args.S >= 1u) {  // the last step's log return
+        const double r = ln_new - ln_last;
+        sum_r = sum_r + r;
+        sum_r2 = sum_r2 + r * r;
     }
     if (active) {
         uint32_t *gb = args.book + d.book_off;
@@ -2077,10 +2183,10 @@ int build_schedule(cae_ensemble *e, const cae_tuning *tn, const uint32_t *ids,
     for (uint32_t m = 0; m < M; ++m) {
         const cae_market &d = e->desc[m];
         const uint32_t c = lclass(d.L) * 8u + aclass(d.A);
-        // packed: last-tick Philox markets whose book fits 4 ticks per lane of a segment, in an
+        // packed: last-tick Philox markets whose book fits 8 ticks per lane of a segment, in an
         // ensemble of small books
         const uint32_t P = maxL <= kPackMaxL ? t.pack[c] : 0u;
-        if (P && (d.flags & 0xFFFFu) == 0u && d.L <= 256u / P) {
+        if (P && (d.flags & 0xFFFFu) == 0u && d.L <= 512u / P) {
             packp[m] = P;
             wpm[m] = 1;
             e->any_pack = true;

@@ -79,6 +79,19 @@ def test_packed_books_of_128_ticks():
     _check(d, 5, [30, 1, 19], _pack_all(2, 8))
 
 
+@pytest.mark.parametrize("G", [4, 16])
+def test_packed_four_books_of_128_ticks(G):
+    """Four markets per wave on books of up to 128 ticks (8 ticks per lane of a 16-lane
+    segment): the agent-sweep shape (A = 16, L = 128), books of 65..128 ticks next to smaller
+    ones in the same waves, mixed agent classes, and offsets wider than the book."""
+    d = np.concatenate([W.uniform(23, 128, 16, 8, 10),
+                        W.uniform(7, 97, 16, 300, 7, n_noise=9, n_mom=4, h=3),
+                        W.uniform(5, 65, 33, 8, 100, n_noise=20, n_mom=0, h=2),
+                        W.uniform(6, 40, 16, 2, 5)])
+    used = _check(d, 12, [40, 7], _pack_all(4, G))
+    assert set(used["pack"].values()) == {4}
+
+
 def test_packed_populations_differ_within_a_wave():
     """Markets of one size class (A below 128) with different populations and grids share waves."""
     rng = np.random.default_rng(3)
