@@ -35,6 +35,9 @@ GROUP_CANDIDATES = (4, 8, 16)
 # A candidate within this fraction of the fastest counts as a tie; ties go to the schedule
 # with fewer waves per market, which leaves the whole ensemble more freedom of group size.
 TIE = 0.02
+# Whole-ensemble stage: classes holding at least HEAVY_SHARE of the events (at most MAX_HEAVY
+# of them) try up to MAX_RUNNERS of their schedules within RUNNER_UP of their probe's fastest.
+HEAVY_SHARE, MAX_HEAVY, MAX_RUNNERS, RUNNER_UP = 0.1, 4, 3, 0.25
 
 
 def classes_of(descs):
@@ -107,6 +110,7 @@ def tune(descs, seed=0, S_probe=None, min_markets=None, cache=None, arch="gfx950
     pack_c = {}
     small_books = int(descs["L"].max()) <= PACK_MAX_L
     ovl_at_g = {}  # class -> {waves per group: fastest clearing share measured there}
+    runners = {}   # class -> [(waves per market, pipelined, overlap, pack)] near its fastest
     cost = {}
     t0 = time.perf_counter()
     for c in sorted(set(cls.tolist())):
@@ -177,6 +181,15 @@ def tune(descs, seed=0, S_probe=None, min_markets=None, cache=None, arch="gfx950
         if best[3]:
             ovl_at_g[c] = {G: min((x for x in ovl if x[2] == G), key=lambda x: x[4])[3]
                            for G in sorted({x[2] for x in ovl})}
+        # runners-up for the whole-ensemble stage: the class's other schedules within
+        # RUNNER_UP of its fastest, fastest first (one per kind of schedule)
+        seen = {(best[0], best[1], best[3], best[5])}
+        runners[c] = []
+        for x in sorted(timings, key=lambda x: x[4]):
+            kind = (x[0], x[1], x[3], x[5])
+            if x[4] <= fastest * (1.0 + RUNNER_UP) and kind not in seen and len(runners[c]) < MAX_RUNNERS:
+                seen.add(kind)
+                runners[c].append(kind)
         # per market-step cost when the class fills the GPU alone
         cost[c] = best[4] * 1e6 / (len(probe) * Sp) * ncu
         cached[key] = {"waves_per_market": wpm[c], "pipelined": bool(pipe_c[c]), "overlap": ovl_c[c],
@@ -199,6 +212,39 @@ def tune(descs, seed=0, S_probe=None, min_markets=None, cache=None, arch="gfx950
             best_g = (G, ms, ovl_g)
     wpm = {c: min(w, best_g[0]) for c, w in wpm.items()}
     ovl_c.update(best_g[2])
+    # whole-ensemble stage: a class's own probe fills the GPU with that class alone, while in a
+    # small mixed ensemble its markets share the chip with the others and the longest chains of
+    # steps set the launch's end.  For the classes that carry most of the events, each runner-up
+    # schedule of the class is tried in the whole ensemble and kept if it is faster by more than
+    # the tie margin.
+    G = best_g[0]
+    S_ens = S_probe or probe_steps(descs)
+
+    def ensemble_tuning():
+        return {"waves_per_group": G, "waves_per_market": {int(c): w for c, w in wpm.items()},
+                "pipelined": {int(c): 1 for c, p in pipe_c.items() if p},
+                "overlap": {int(c): k for c, k in ovl_c.items() if k},
+                "pack": {int(c): P for c, P in pack_c.items() if P}}
+
+    work = {c: float(descs["A"][cls == c].astype(np.float64).sum()) for c in set(cls.tolist())}
+    total = sum(work.values())
+    heavy = [c for c in sorted(work, key=lambda c: -work[c]) if work[c] >= HEAVY_SHARE * total][:MAX_HEAVY]
+    if len(work) > 1 and any(runners.get(c) for c in heavy):  # one class: its probe was the ensemble
+        current = _time_launch(descs, seed, ensemble_tuning(), S_ens)
+        for c in heavy:
+            for w, pipe, k, P in runners.get(c, []):
+                if w > G or (pipe and G < 2):
+                    continue
+                keep = (wpm[c], pipe_c[c], ovl_c.get(c, 0), pack_c[c])
+                wpm[c], pipe_c[c], ovl_c[c], pack_c[c] = w, pipe, k, P
+                ms = _time_launch(descs, seed, ensemble_tuning(), S_ens)
+                if log:
+                    log("ensemble: class %2d as (wpm %d, pipelined %d, overlap %d, pack %d): %.3f ms (current %.3f)" %
+                        (c, w, pipe, k, P, ms, current))
+                if ms < current * (1.0 - TIE):
+                    current = ms
+                else:
+                    wpm[c], pipe_c[c], ovl_c[c], pack_c[c] = keep
     if cache:
         allc = {}
         if os.path.exists(cache):
