@@ -369,6 +369,8 @@ __global__ void __launch_bounds__(256) mlp_predict(const PredArgs a)
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
 constexpr uint32_t kTrainRows = 16;
+constexpr uint32_t kRowWaves = 16;   // waves of an mlp_train_rows workgroup: one 16-column tile each at H = 256
+constexpr uint32_t kParamSplit = 4;  // waves that reduce one weight-gradient tile, each a quarter of the batch
 constexpr uint32_t kTrainMaxH = 256;
 constexpr uint32_t kTrainMaxIn = 32;
 constexpr uint32_t kTrainPad = 8;  // bf16 elements of padding per LDS row
@@ -416,7 +418,7 @@ struct TrainArgs {
     uint32_t tiles1, tiles2, tiles3;  // gradient tiles of W1|b1, W2|b2, W3|b3
 };
 
-__global__ void __launch_bounds__(256) mlp_train_rows(const TrainArgs a)
+__global__ void __launch_bounds__(kRowWaves * 64) mlp_train_rows(const TrainArgs a)
 {
     extern __shared__ __align__(16) unsigned char tlds[];
     const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
@@ -431,7 +433,7 @@ __global__ void __launch_bounds__(256) mlp_train_rows(const TrainArgs a)
     float *z1s = reinterpret_cast<float *>(dzs + kTrainRows * ldh);  // [16][H]
     float *z2s = z1s + kTrainRows * H;
     // inputs of the rows (zero past the batch), their transposed copy, and a zeroed dy tile
-    for (uint32_t i = threadIdx.x; i < kTrainRows * 32u; i += 256u) {
+    for (uint32_t i = threadIdx.x; i < kTrainRows * 32u; i += kRowWaves * 64u) {
         const uint32_t rr = i / 32u, c = i % 32u, row = row0 + rr;
         uint16_t v = 0;
         if (row < a.B && c < a.din) {
@@ -444,7 +446,7 @@ __global__ void __launch_bounds__(256) mlp_train_rows(const TrainArgs a)
     }
     __syncthreads();
     // layer 1: z1 = x W1 + b1, h1 = silu(z1)  (one reduction step: d_in <= 32)
-    for (uint32_t j = wave; j < ct; j += 4u) {
+    for (uint32_t j = wave; j < ct; j += kRowWaves) {
         const uint32_t n = 16u * j + r;
         uint16_t e[8];
 #pragma unroll
@@ -467,7 +469,7 @@ __global__ void __launch_bounds__(256) mlp_train_rows(const TrainArgs a)
     }
     __syncthreads();
     // layer 2: z2 = h1 W2 + b2, B fragments from the transposed copy W2T[n][k]
-    for (uint32_t j = wave; j < ct; j += 4u) {
+    for (uint32_t j = wave; j < ct; j += kRowWaves) {
         const uint32_t n = 16u * j + r;
         v4f acc = {0.f, 0.f, 0.f, 0.f};
         for (uint32_t k0 = 0; k0 < H; k0 += 32u)
@@ -523,7 +525,7 @@ __global__ void __launch_bounds__(256) mlp_train_rows(const TrainArgs a)
     }
     __syncthreads();
     // dz2 = (dy W3^T) silu'(z2)  (one reduction step: d_out <= 16)
-    for (uint32_t j = wave; j < ct; j += 4u) {
+    for (uint32_t j = wave; j < ct; j += kRowWaves) {
         const uint32_t n = 16u * j + r;
         uint16_t e[8];
 #pragma unroll
@@ -544,7 +546,7 @@ __global__ void __launch_bounds__(256) mlp_train_rows(const TrainArgs a)
     }
     __syncthreads();
     // dz1 = (dz2 W2^T) silu'(z1): B fragments W2[n][k], eight consecutive k
-    for (uint32_t j = wave; j < ct; j += 4u) {
+    for (uint32_t j = wave; j < ct; j += kRowWaves) {
         const uint32_t n = 16u * j + r;
         v4f acc = {0.f, 0.f, 0.f, 0.f};
         for (uint32_t k0 = 0; k0 < H; k0 += 32u)
@@ -569,7 +571,7 @@ __device__ __forceinline__ float adam_one(const TrainArgs &a, uint64_t i, float 
     return pi;
 }
 
-__global__ void __launch_bounds__(256) mlp_train_params(const TrainArgs a)
+__global__ void __launch_bounds__(kParamSplit * 64) mlp_train_params(const TrainArgs a)
 {
     const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
     const uint32_t r = lane & 15u, g = lane >> 4;
@@ -578,7 +580,7 @@ __global__ void __launch_bounds__(256) mlp_train_params(const TrainArgs a)
         for (uint32_t i = 0; i < a.Bp / kTrainRows; ++i) s += a.loss_part[i];
         a.loss[0] = s * a.inv_n;
     }
-    uint32_t tile = blockIdx.x * 4u + wave;
+    uint32_t tile = blockIdx.x;  // kParamSplit waves per tile
     const uint32_t H = a.H, din = a.din, dout = a.dout, ct = H / 16u;
     // which gradient: [A^T ; 1] B over the batch, A the layer's input, B its output gradient
     const uint16_t *AT, *BT;
@@ -606,12 +608,21 @@ __global__ void __launch_bounds__(256) mlp_train_params(const TrainArgs a)
     const bool arow = i < M, brow = j < N;  // rows >= Bp of the transposed arrays do not exist
     const uint16_t *ap = AT + (size_t)(arow ? i : 0) * a.Bp + 8u * g;
     const uint16_t *bp = BT + (size_t)(brow ? j : 0) * a.Bp + 8u * g;
+    // wave w reduces the batch chunks w, w + kParamSplit, ... of 32 rows; the partial sums are
+    // then added in wave order (a fixed order: deterministic)
+    __shared__ v4f part[kParamSplit][64];
     v4f acc = {0.f, 0.f, 0.f, 0.f};
-    for (uint32_t b0 = 0; b0 < a.Bp; b0 += 32u) {
+    for (uint32_t b0 = 32u * wave; b0 < a.Bp; b0 += 32u * kParamSplit) {
         const v8bf av = arow ? ld8(ap + b0) : (i == M ? ones : zero);
         const v8bf bv = brow ? ld8(bp + b0) : zero;
         acc = mfma32(av, bv, acc);
     }
+    part[wave][lane] = acc;
+    __syncthreads();
+    if (wave != 0u) return;
+    acc = part[0][lane];
+#pragma unroll
+    for (uint32_t w = 1; w < kParamSplit; ++w) acc += part[w][lane];
     const uint32_t jc = tj * 16u + r;
     if (jc >= N) return;
 #pragma unroll
@@ -858,9 +869,9 @@ int train_step_impl(const cae_mlp *net, const float *x, const float *target, con
     a.tiles2 = (H / 16u + 1u) * ct;
     a.tiles3 = H / 16u + 1u;
     const size_t lds = 2ull * (2u * kTrainRows * 32u + 3ull * kTrainRows * (H + kTrainPad)) + 8ull * kTrainRows * H;
-    hipLaunchKernelGGL(mlp_train_rows, dim3(a.Bp / kTrainRows), dim3(256), lds, s, a);
+    hipLaunchKernelGGL(mlp_train_rows, dim3(a.Bp / kTrainRows), dim3(kRowWaves * 64u), lds, s, a);
     const uint32_t tiles = a.tiles1 + a.tiles2 + a.tiles3;
-    hipLaunchKernelGGL(mlp_train_params, dim3((tiles + 3u) / 4u), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(mlp_train_params, dim3(tiles), dim3(kParamSplit * 64u), 0, s, a);
     return launch_status();
 }
 
