@@ -39,6 +39,7 @@ enum Kind : int {
     K_PHILOX_ROUNDS = 11,
     K_GEN_NOISE = 12,
     K_LDS_RW_B64 = 13,
+    K_GEN_NOISE4 = 14,
 };
 
 // Shader-clock cycles and 100 MHz real-time ticks of the timed loop, per workgroup.
@@ -252,6 +253,7 @@ __global__ void __launch_bounds__(1024) ub_philox_rounds(uint32_t *out, uint64_t
 // The engine's NOISE-order code for 2 x 64 agents per wave and iteration (two rows at uniform
 // bases, as the engine's order loop issues them), one market-step per `rows` iterations.  The
 // book word 2 tick + side and the quantity of every order are folded into one register.
+template <int NR>
 __global__ void __launch_bounds__(1024) ub_gen_noise(uint32_t *out, uint64_t *clk, uint32_t iters, uint32_t k0,
                                                      uint32_t k1)
 {
@@ -266,15 +268,18 @@ __global__ void __launch_bounds__(1024) ub_gen_noise(uint32_t *out, uint64_t *cl
     constexpr uint32_t rows = 8;  // 16 rows of 64 agents per market-step (A = 1024)
     for (uint32_t i = 0; i < iters; i += rows) {
         const PhiloxStep gen(i / rows, __builtin_amdgcn_readfirstlane(m), k0, k1);
-        for (uint32_t j = 0; j < rows; ++j) {
-            const uint32_t bb = j * 128u;
-            uint32_t w0, w1, w2, w3, x0, x1, x2, x3;
-            gen.words4_row(bb, lane, w0, w1, w2, w3);
-            gen.words4_row(bb + 64u, lane, x0, x1, x2, x3);
-            const uint32_t wa = 2u * (uint32_t)clamp_tick(base + (int)__umulhi(w1, span), top) + (w0 >> 31);
-            const uint32_t wb = 2u * (uint32_t)clamp_tick(base + (int)__umulhi(x1, span), top) + (x0 >> 31);
-            acc = xor3(acc, wa, qty1(w2, Q));
-            acc = xor3(acc, wb, qty1(x2, Q));
+        for (uint32_t j = 0; j < rows * 2u / NR; ++j) {
+            const uint32_t bb = j * 64u * NR;
+#pragma unroll
+            for (int r = 0; r < NR; r += 2) {
+                uint32_t w0, w1, w2, w3, x0, x1, x2, x3;
+                gen.words4_row(bb + 64u * r, lane, w0, w1, w2, w3);
+                gen.words4_row(bb + 64u * r + 64u, lane, x0, x1, x2, x3);
+                const uint32_t wa = 2u * (uint32_t)clamp_tick(base + (int)__umulhi(w1, span), top) + (w0 >> 31);
+                const uint32_t wb = 2u * (uint32_t)clamp_tick(base + (int)__umulhi(x1, span), top) + (x0 >> 31);
+                acc = xor3(acc, wa, qty1(w2, Q));
+                acc = xor3(acc, wb, qty1(x2, Q));
+            }
         }
     }
     __syncthreads();
@@ -293,7 +298,8 @@ extern "C" {
 // Runs one microbenchmark: `blocks` workgroups of `threads` threads (64..1024), `iters` iterations
 // (8 operations per lane for the single-instruction kinds; 80 instructions per lane for
 // philox_rounds; 16 LDS words read or written per lane for lds_rw_b64; 128 agent events per wave
-// for gen_noise, whose iters must be a multiple of 8).  Writes the elapsed milliseconds to *ms and, per workgroup, the shader
+// for gen_noise and gen_noise4 (two or four rows of agents per pass), whose iters must be a
+// multiple of 8).  Writes the elapsed milliseconds to *ms and, per workgroup, the shader
 // clock cycles and 100 MHz real-time ticks of its timed loop to clk[2*b], clk[2*b+1].  out must
 // hold blocks*threads words and clk 2*blocks 64-bit words of device memory.  Returns 0, or -1 for
 // an unknown kind, -4 for a HIP error.
@@ -326,7 +332,15 @@ int cae_ubench_run(int kind, uint32_t blocks, uint32_t threads, uint32_t iters, 
             (void)hipEventDestroy(e1);
             return -1;
         }
-        hipLaunchKernelGGL(ub_gen_noise, g, b, 0, nullptr, out, clk, iters, 1u, 0u);
+        hipLaunchKernelGGL(ub_gen_noise<2>, g, b, 0, nullptr, out, clk, iters, 1u, 0u);
+        break;
+    case K_GEN_NOISE4:
+        if (iters % 8u) {
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            return -1;
+        }
+        hipLaunchKernelGGL(ub_gen_noise<4>, g, b, 0, nullptr, out, clk, iters, 1u, 0u);
         break;
     default:
         (void)hipEventDestroy(e0);

@@ -25,10 +25,12 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 KINDS = {"v_add_u32": 0, "v_xor_b32": 1, "v_bitop3_b32": 2, "v_mul_hi_u32": 3,
          "v_mul_lo_u32": 4, "v_mad_u64_u32": 5, "ds_add_u32_conflict_free": 6,
          "ds_add_u32_window66": 7, "v_fma_f32": 8, "v_fma_f64": 9,
-         "mad_u64_const": 10, "philox_rounds": 11, "gen_noise_events": 12, "ds_rw_b64_words": 13}
+         "mad_u64_const": 10, "philox_rounds": 11, "gen_noise_events": 12, "ds_rw_b64_words": 13,
+         "gen_noise_events_4rows": 14}
 # operations per lane and loop iteration of each kernel
 OPS_PER_ITER = {k: 8 for k in KINDS}
-OPS_PER_ITER.update({"philox_rounds": 80, "gen_noise_events": 2, "ds_rw_b64_words": 16})
+OPS_PER_ITER.update({"philox_rounds": 80, "gen_noise_events": 2, "ds_rw_b64_words": 16,
+                     "gen_noise_events_4rows": 2})
 
 
 def measure(iters=4096, reps=3):
@@ -50,7 +52,7 @@ def measure(iters=4096, reps=3):
             for _ in range(reps):
                 ms = C.c_float()
                 it = iters // 4 if name.startswith("ds_") else iters
-                if name in ("philox_rounds", "gen_noise_events"):  # ~80 instructions per iteration
+                if name in ("philox_rounds", "gen_noise_events", "gen_noise_events_4rows"):  # ~80 per iteration
                     it = max(8, iters // 8)
                 rc = lib.cae_ubench_run(k, blocks, threads, it, out.data_ptr(), clk.data_ptr(),
                                         C.byref(ms))
@@ -96,6 +98,7 @@ def summary(res, nw=16):
            "mad_in_mix_slots": (round_slots - 2.0 * xor3) / 2.0,
            "gen_events_per_clk_cu": 64.0 * g("gen_noise_events"),
            "gen_slots_per_event": 64.0 * full / (64.0 * g("gen_noise_events")),
+           "gen4_events_per_clk_cu": 64.0 * g("gen_noise_events_4rows"),
            "lds_window_lane_atomics_per_clk_cu": 64.0 * g("ds_add_u32_window66"),
            "lds_conflict_free_lane_atomics_per_clk_cu": 64.0 * g("ds_add_u32_conflict_free"),
            "lds_rw_b64_lane_words_per_clk_cu": 64.0 * g("ds_rw_b64_words"),
