@@ -11,7 +11,9 @@
 //     ONE wave then clears the whole book: each lane owns TPL contiguous ticks, in-lane serial
 //     sums plus a wave64 DPP scan give D and S, two ballots at the crossing of D and S give the
 //     maximal volume and its lowest tick (no max reduction), and the fill uses the closed form
-//        fill_bid(q) = min(D(q), V*) - min(D(q+1), V*),  fill_ask(q) = min(S(q), V*) - min(S(q-1), V*).
+//        fill_bid(q) = min(D(q), V*) - min(D(q+1), V*),  fill_ask(q) = min(S(q), V*) - min(S(q-1), V*)
+//     (books of at most 4 ticks per lane keep the residuals as max(D(q) - V*, 0) - max(D(q+1) - V*, 0)
+//     and the ask counterpart).
 //     No cross-wave scan pass and only two barriers per step; the clearing wave rotates with the
 //     step so the clearing work spreads over the CU's four SIMDs.  Optionally (last-tick model)
 //     the other waves generate the NEXT step's orders while the clearing runs, aggregated by
@@ -142,6 +144,13 @@ struct ClearOut {
     uint32_t p, v, bb, ba;  // clearing tick, volume, best bid / best ask after the fill (kNone: empty)
 };
 
+// max(x - v, 0) in one instruction (v_sub_u32 with clamp).  With it the price-priority fill is
+// one subtract per tick and side: D(q) - min(D(q), V*) = max(D(q) - V*, 0) is the demand at or
+// above q that stays unmatched, so the residual bids at q are max(D(q) - V*, 0) -
+// max(D(q+1) - V*, 0), and the residual asks max(S(q) - V*, 0) - max(S(q-1) - V*, 0): the same
+// numbers as b - (min(D(q), V*) - min(D(q+1), V*)) and its ask counterpart, with fewer steps.
+__device__ __forceinline__ uint32_t unmatched(uint32_t x, uint32_t v) { return __builtin_elementwise_sub_sat(x, v); }
+
 // Reads / writes CH consecutive (bid, ask) pairs starting at tick q of an LDS book.
 template <int CH>
 __device__ __forceinline__ void load_pairs(const uint32_t *bk, uint32_t q, uint32_t (&b)[CH], uint32_t (&k)[CH])
@@ -191,9 +200,10 @@ __device__ __forceinline__ uint32_t crossing_lane(bool pred)
 
 // Clearing of a book of at most 4 ticks per lane, its ticks held in registers throughout: the
 // demand D and supply S of every tick are formed once, the volume pass and the fill reuse them,
-// and the fill takes running minima with V*: fill_b(q) = min(D(q), V*) - min(D(q+1), V*),
-// fill_s(q) = min(S(q), V*) - min(S(q-1), V*).  Every instruction here is on the step's critical
-// path (one wave, the rest of the market waiting), so the pass is kept short.
+// and the fill leaves the residual of each tick as a difference of unmatched quantities:
+// max(D(q) - V*, 0) - max(D(q+1) - V*, 0) bids, max(S(q) - V*, 0) - max(S(q-1) - V*, 0) asks.
+// Every instruction here is on the step's critical path (one wave, the rest of the market
+// waiting), so the pass is kept short.
 template <int TPL>
 __device__ __forceinline__ ClearOut clear_small(uint32_t *__restrict__ bk, uint32_t lane)
 {
@@ -229,14 +239,14 @@ __device__ __forceinline__ ClearOut clear_small(uint32_t *__restrict__ bk, uint3
         for (int j = 0; j < TPL; ++j) pj += Sq[j] < vs ? 1u : 0u;
         out.p = readlane(pj, crossing_lane(Sq[TPL - 1] >= vs));
     }
-    uint32_t md = min(D[0], vs), ms = min(Sb, vs);
+    uint32_t ud = unmatched(D[0], vs), us = unmatched(Sb, vs);
 #pragma unroll
     for (int j = 0; j < TPL; ++j) {
-        const uint32_t md1 = min(D[j + 1], vs), ms1 = min(Sq[j], vs);
-        b[j] -= md - md1;
-        k[j] -= ms1 - ms;
-        md = md1;
-        ms = ms1;
+        const uint32_t ud1 = unmatched(D[j + 1], vs), us1 = unmatched(Sq[j], vs);
+        b[j] = ud - ud1;
+        k[j] = us1 - us;
+        ud = ud1;
+        us = us1;
     }
     store_pairs<TPL>(bk, q0, b, k);
     uint32_t hb = kNone, la = kNone;
@@ -1559,14 +1569,14 @@ __device__ __forceinline__ ClearOut clear_seg(uint32_t *__restrict__ bk, uint32_
         for (int j = 0; j < TPL; ++j) pj += Sq[j] < vs ? 1u : 0u;
         out.p = lane_value(pj, seg_crossing_lane<SEGLOG>(Sq[TPL - 1] >= vs, base));
     }
-    uint32_t md = min(D[0], vs), ms = min(Sb, vs);
+    uint32_t ud = unmatched(D[0], vs), us = unmatched(Sb, vs);
 #pragma unroll
     for (int j = 0; j < TPL; ++j) {
-        const uint32_t md1 = min(D[j + 1], vs), ms1 = min(Sq[j], vs);
-        b[j] -= md - md1;
-        k[j] -= ms1 - ms;
-        md = md1;
-        ms = ms1;
+        const uint32_t ud1 = unmatched(D[j + 1], vs), us1 = unmatched(Sq[j], vs);
+        b[j] = ud - ud1;
+        k[j] = us1 - us;
+        ud = ud1;
+        us = us1;
     }
     if (wr) store_pairs<TPL>(bk, q0, b, k);
     uint32_t hb = kNone, la = kNone;
@@ -1626,18 +1636,18 @@ __device__ __forceinline__ ClearOut clear_seg_lean(uint32_t *__restrict__ bk, ui
         }
         out.p = lane_value(pj, seg_crossing_lane<SEGLOG>(ia >= vs, base));
     }
-    uint32_t md = min(D0, vs), ms = min(Sb, vs);
+    uint32_t ud = unmatched(D0, vs), us = unmatched(Sb, vs);
     d = D0;
     sq = Sb;
 #pragma unroll
     for (int j = 0; j < TPL; ++j) {
         d -= b[j];
         sq += k[j];
-        const uint32_t md1 = min(d, vs), ms1 = min(sq, vs);
-        b[j] -= md - md1;
-        k[j] -= ms1 - ms;
-        md = md1;
-        ms = ms1;
+        const uint32_t ud1 = unmatched(d, vs), us1 = unmatched(sq, vs);
+        b[j] = ud - ud1;
+        k[j] = us1 - us;
+        ud = ud1;
+        us = us1;
     }
     if (wr) store_pairs<TPL>(bk, q0, b, k);
     uint32_t hb = kNone, la = kNone;
