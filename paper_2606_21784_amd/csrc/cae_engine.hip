@@ -1595,11 +1595,53 @@ __device__ __forceinline__ ClearOut clear_seg(uint32_t *__restrict__ bk, uint32_
     return out;
 }
 
-// clear_seg for books of 8 ticks per lane: the same passes, with the demand and supply of each
-// tick re-formed by running sums in every pass instead of held in arrays, so that only the 16
-// book words stay live (the packed kernels run at their register limit).
-template <int TPL, int SEGLOG>
-__device__ __forceinline__ ClearOut clear_seg_lean(uint32_t *__restrict__ bk, uint32_t ll, uint32_t base, bool wr)
+// Segments of 16 lanes are DPP rows, so every per-segment value comes from row operations in
+// registers (no lane permute through the LDS): a row reduction (row_shr by 1, 2, 4, 8, with the
+// reduction's identity for lanes shifted in from outside the row) leaves the row's result in its
+// last lane, and row_newbcast:15 hands that lane's value to the whole row.
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_or(uint32_t identity, uint32_t x)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)identity, (int)x, CTRL, 0xf, 0xf, false);
+}
+
+__device__ __forceinline__ uint32_t row_last(uint32_t x) { return dpp_or<0x15F>(0u, x); }
+
+__device__ __forceinline__ uint32_t row_sum(uint32_t x)
+{
+    x += dpp_or<0x111>(0u, x);
+    x += dpp_or<0x112>(0u, x);
+    x += dpp_or<0x114>(0u, x);
+    x += dpp_or<0x118>(0u, x);
+    return row_last(x);
+}
+
+__device__ __forceinline__ uint32_t row_max(uint32_t x)
+{
+    x = max(x, dpp_or<0x111>(0u, x));
+    x = max(x, dpp_or<0x112>(0u, x));
+    x = max(x, dpp_or<0x114>(0u, x));
+    x = max(x, dpp_or<0x118>(0u, x));
+    return row_last(x);
+}
+
+__device__ __forceinline__ uint32_t row_min(uint32_t x)
+{
+    x = min(x, dpp_or<0x111>(kNone, x));
+    x = min(x, dpp_or<0x112>(kNone, x));
+    x = min(x, dpp_or<0x114>(kNone, x));
+    x = min(x, dpp_or<0x118>(kNone, x));
+    return row_last(x);
+}
+
+// One clearing pass over the book of each 16-lane segment (four books per wave), TPL ticks per
+// lane (ll: the lane's index in its segment; wr: the segment holds a market).  By the definitions:
+// V* = max over ticks of min(D, S) (a row maximum of the lanes' maxima); since S rises with the
+// tick, the lowest tick with V = V* is the number of ticks with S < V* (a row sum); the best
+// quotes after the fill are a row maximum and minimum.  D and S of each tick are re-formed by
+// running sums in every pass, so only the book words stay live.  Segment-uniform result.
+template <int TPL>
+__device__ __forceinline__ ClearOut clear_row(uint32_t *__restrict__ bk, uint32_t ll, bool wr)
 {
     const uint32_t q0 = ll * TPL;
     uint32_t b[TPL], k[TPL];
@@ -1611,30 +1653,27 @@ __device__ __forceinline__ ClearOut clear_seg_lean(uint32_t *__restrict__ bk, ui
         sa += k[j];
     }
     uint32_t ib = sb, ia = sa;
-    seg_scan_add2<SEGLOG>(ib, ia);
-    constexpr uint32_t kSeg = 1u << SEGLOG;
-    const uint32_t Tb = lane_value(ib, base + kSeg - 1u);
-    const uint32_t D0 = Tb - (ib - sb);  // demand at the lane's first tick
-    const uint32_t Sb = ia - sa;         // asks below the lane's first tick
-    uint32_t vc = Sb, d = D0, sq = Sb;
+    seg_scan_add2<4>(ib, ia);
+    const uint32_t D0 = row_last(ib) - (ib - sb);  // demand at the lane's first tick
+    const uint32_t Sb = ia - sa;                    // asks below the lane's first tick
+    uint32_t mv = 0, d = D0, sq = Sb;
 #pragma unroll
     for (int j = 0; j < TPL; ++j) {
         sq += k[j];
-        vc = max(vc, min(d, sq));
+        mv = max(mv, min(d, sq));
         d -= b[j];
     }
-    // sq = S of the lane's top tick (= ia), d + b[TPL - 1] = D of that tick
     ClearOut out;
-    out.v = lane_value(vc, seg_crossing_lane<SEGLOG>(ia >= d + b[TPL - 1], base));
+    out.v = row_max(mv);
     const uint32_t vs = out.v;
     {
-        uint32_t pj = q0, t = Sb;
+        uint32_t cnt = 0, t = Sb;
 #pragma unroll
         for (int j = 0; j < TPL; ++j) {
             t += k[j];
-            pj += t < vs ? 1u : 0u;
+            cnt += t < vs ? 1u : 0u;
         }
-        out.p = lane_value(pj, seg_crossing_lane<SEGLOG>(ia >= vs, base));
+        out.p = row_sum(cnt);
     }
     uint32_t ud = unmatched(D0, vs), us = unmatched(Sb, vs);
     d = D0;
@@ -1657,12 +1696,8 @@ __device__ __forceinline__ ClearOut clear_seg_lean(uint32_t *__restrict__ bk, ui
 #pragma unroll
     for (int j = TPL - 1; j >= 0; --j)
         if (k[j] != 0) la = q0 + j;
-    const uint32_t mb = seg_bits<SEGLOG>(ballot(hb != kNone), base);
-    const uint32_t ma = seg_bits<SEGLOG>(ballot(la != kNone), base);
-    const uint32_t bbv = lane_value(hb, base + (mb ? 31u - (uint32_t)__builtin_clz(mb) : 0u));
-    const uint32_t bav = lane_value(la, base + (ma ? (uint32_t)__builtin_ctz(ma) : 0u));
-    out.bb = mb ? bbv : kNone;
-    out.ba = ma ? bav : kNone;
+    out.bb = row_max(hb + 1u) - 1u;  // kNone + 1 = 0: a row without bids gives kNone back
+    out.ba = row_min(la);
     return out;
 }
 
@@ -1670,8 +1705,12 @@ template <int SEGLOG>
 __device__ __forceinline__ ClearOut clear_seg_dispatch(uint32_t *bk, uint32_t tpl, uint32_t ll, uint32_t base,
                                                        bool wr)
 {
-    if constexpr (SEGLOG == 4) {  // 16-lane segments hold books of up to 128 ticks
-        if (tpl >= 8u) return clear_seg_lean<8, SEGLOG>(bk, ll, base, wr);
+    if constexpr (SEGLOG == 4) {  // 16-lane segments (DPP rows) hold books of up to 128 ticks
+        (void)base;
+        if (tpl >= 8u) return clear_row<8>(bk, ll, wr);
+        if (tpl >= 4u) return clear_row<4>(bk, ll, wr);
+        if (tpl == 2u) return clear_row<2>(bk, ll, wr);
+        return clear_row<1>(bk, ll, wr);
     }
     if (tpl >= 4u) return clear_seg<4, SEGLOG>(bk, ll, base, wr);
     if (tpl == 2u) return clear_seg<2, SEGLOG>(bk, ll, base, wr);
