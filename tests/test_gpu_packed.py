@@ -171,3 +171,76 @@ def test_packed_many_launches():
     ens.close()
     _, rbk = O.run(d, 2, 36)
     np.testing.assert_array_equal(bk, rbk)
+
+
+def _segment_books(L, seg, rng):
+    """Books whose crossing of demand and supply lands on the edges of the ticks a lane of a
+    seg-lane segment owns, on the first and last tick or nowhere, with ties over a plateau,
+    separated and one-sided books, and large quantities.  Returns (n, 2, L) uint32."""
+    tpl = 1
+    while seg * tpl < L:
+        tpl *= 2
+    edges = sorted({q for e in range(0, L + 1, tpl) for q in (e - 1, e, e + 1) if 0 <= q < L})
+    out = []
+    for q in edges:
+        for below in (0, 1, 2):
+            b = np.zeros((2, L), np.uint64)
+            b[1, : q + 1] = 3
+            b[0, q:] = 2
+            b[0, q] += below * 3 * q
+            out.append(b)
+        b = np.zeros((2, L), np.uint64)  # a plateau of equal volume over [q, top]
+        b[0, L - 1] = 7
+        b[1, q] = 7
+        out.append(b)
+        b = np.zeros((2, L), np.uint64)  # separated: nothing trades
+        b[0, :q] = 5
+        b[1, q:] = 5
+        out.append(b)
+    for side in (0, 1):
+        b = np.zeros((2, L), np.uint64)
+        b[side] = rng.integers(0, 9, L)
+        out.append(b)
+    for _ in range(12):
+        b = np.zeros((2, L), np.uint64)  # sparse, often on lane edges, some large quantities
+        for side in (0, 1):
+            k = int(rng.integers(1, 5))
+            pool = edges if rng.random() < 0.5 else list(range(L))
+            b[side, rng.choice(pool, size=k)] += rng.choice([1, 2, 5, (1 << 29) // k], size=k).astype(np.uint64)
+        out.append(b)
+    return np.stack(out).astype(np.uint32)
+
+
+@pytest.mark.parametrize("P", [2, 4])
+def test_packed_clearing_structured_books(P):
+    """The packed clearing (one lane segment per book, DPP-row reductions for 16-lane segments)
+    on books built to cross on the edges of a lane's ticks, on the first or last tick or nowhere,
+    with ties, with nothing to trade, one-sided and with large quantities: each market starts
+    from such a book (cae_write_state) and steps once with one agent of one share, against the
+    oracle started from the same state."""
+    E = _engine()
+    rng = np.random.default_rng(40 + P)
+    for L in (1, 2, 7, 15, 16, 17, 31, 32, 33, 48, 63, 64, 65, 100, 127, 128):
+        if L > 512 // P:
+            continue
+        books = _segment_books(L, 64 // P, rng)
+        n = books.shape[0]
+        d = W.uniform(n, L, 1, 0, 1, h=min(2, L - 1))
+        st = np.zeros(n, O.STATE_DTYPE)
+        st["last"] = rng.integers(0, L, n)
+        st["prev"] = rng.integers(0, L, n)
+        st["ref2"] = 2 * st["last"]
+        st["steps_done"] = books.reshape(n, -1).astype(np.uint64).sum(axis=1) + 1  # the book's shares fit
+        bk = books.reshape(-1)
+        ens = E.Ensemble(d, 3, tuning=_pack_all(P))
+        assert set(ens.tuning()["pack"].values()) == {P}, L
+        ens.write_state(st, bk)
+        ens.step(1)
+        gst, gbk = ens.read_state(), ens.read_books()
+        ens.close()
+        rst, rbk = O.run(d, 3, 1, states=st, book=bk)
+        np.testing.assert_array_equal(gbk, rbk, err_msg="L=%d" % L)
+        for f in INT_FIELDS:
+            np.testing.assert_array_equal(gst[f], rst[f], err_msg="L=%d %s" % (L, f))
+        for f in ("sum_r", "sum_r2"):
+            np.testing.assert_allclose(gst[f], rst[f], rtol=1e-6, atol=1e-300, err_msg=f)
