@@ -38,6 +38,8 @@ TIE = 0.02
 # Whole-ensemble stage: classes holding at least HEAVY_SHARE of the events (at most MAX_HEAVY
 # of them) try up to MAX_RUNNERS of their schedules within RUNNER_UP of their probe's fastest.
 HEAVY_SHARE, MAX_HEAVY, MAX_RUNNERS, RUNNER_UP = 0.1, 4, 3, 0.25
+# The overlapped schedule is also probed at the second fastest plain width within this fraction.
+OVL_SECOND = 0.3
 
 
 def classes_of(descs):
@@ -77,6 +79,18 @@ def probe_steps(descs, S_min=20, S_max=1000, events=PROBE_EVENTS):
     return int(max(1, min(S, guard // 2 - 1)))
 
 
+def _pick(timings):
+    """The schedule kept from a class's probe timings (w, pipelined, G, overlap, ms, pack): the
+    fewest waves per market among the near-fastest (plain candidates come first, in increasing
+    order of waves per market).  The overlapped candidates are one family, represented by its
+    fastest member: the tie margin prefers a narrower schedule, not the first of several
+    clearing shares that differ by noise."""
+    fastest = min(x[4] for x in timings)
+    ovl = [x for x in timings if x[3]]
+    family = [x for x in timings if not x[3]] + ([min(ovl, key=lambda x: x[4])] if ovl else [])
+    return next(x for x in family if x[4] <= fastest * (1.0 + TIE))
+
+
 def _probe_set(descs, idx, min_markets, rng):
     """Markets of one class for probing: the class's own descriptors, replicated or sampled so
     that the probe fills the GPU (min_markets) without exceeding it by much."""
@@ -109,8 +123,8 @@ def tune(descs, seed=0, S_probe=None, min_markets=None, cache=None, arch="gfx950
     ovl_c = {}
     pack_c = {}
     small_books = int(descs["L"].max()) <= PACK_MAX_L
-    ovl_at_g = {}  # class -> {waves per group: fastest clearing share measured there}
     runners = {}   # class -> [(waves per market, pipelined, overlap, pack)] near its fastest
+    timings_c = {}  # class -> every probed (waves per market, pipelined, G, overlap, ms, pack)
     cost = {}
     t0 = time.perf_counter()
     for c in sorted(set(cls.tolist())):
@@ -134,7 +148,6 @@ def tune(descs, seed=0, S_probe=None, min_markets=None, cache=None, arch="gfx950
         cands = [(1, False, G, 0, P) for P in PACK_CANDIDATES for G in (4, 8)
                  if packable and int(probe["L"].max()) <= 512 // P]
         cands += [(w, False, max(4, w), 0, 0) for w in WPM_CANDIDATES] + [(1, True, G, 0, 0) for G in PIPE_GROUPS]
-        best = None
         timings = []
 
         def run(w, pipe, G, k, P=0):
@@ -156,31 +169,26 @@ def tune(descs, seed=0, S_probe=None, min_markets=None, cache=None, arch="gfx950
 
         for w, pipe, G, k, P in cands:
             run(w, pipe, G, k, P)
-        # overlapped lock-step at the fastest plain lock-step width, one or two markets per
-        # workgroup: the clearing wave takes from none to all of an even share of the market's
-        # rows of 64 agents (at most 5 steps)
-        lock = min((x for x in timings if x[0] >= 2 and not x[1] and not x[5]), key=lambda x: x[4])
-        w = lock[0]
+        # overlapped lock-step at the fastest plain lock-step width (and at the second fastest
+        # when it is within OVL_SECOND of it: a long clearing, as for books of 1024 ticks, can
+        # favour more generating waves), one or two markets per workgroup: the clearing wave
+        # takes from none to all of an even share of the market's rows of 64 agents (at most 5
+        # steps)
+        plain = sorted((x for x in timings if x[0] >= 2 and not x[1] and not x[5]), key=lambda x: x[4])
+        widths = [plain[0][0]] + [x[0] for x in plain[1:2] if x[4] <= plain[0][4] * (1.0 + OVL_SECOND)]
         rows = -(-int(probe["A"].max()) // 64)
-        even = rows // w
-        for G in sorted({max(4, w), min(16, 2 * max(4, w))}):
-            for share in sorted({min(even, (even * j + 3) // 4) for j in range(5)}):
-                run(w, False, G, share + 1)
+        for w in widths:
+            even = rows // w
+            for G in sorted({max(4, w), min(16, 2 * max(4, w))}):
+                for share in sorted({min(even, (even * j + 3) // 4) for j in range(5)}):
+                    run(w, False, G, share + 1)
         fastest = min(x[4] for x in timings)
-        # fewest waves per market among the near-fastest (plain candidates come first, in
-        # increasing order of waves per market).  The overlapped candidates are one family,
-        # represented by its fastest member: the tie margin prefers a narrower schedule, not
-        # the first of several clearing shares that differ by noise.
-        ovl = [x for x in timings if x[3]]
-        family = [x for x in timings if not x[3]] + ([min(ovl, key=lambda x: x[4])] if ovl else [])
-        best = next(x for x in family if x[4] <= fastest * (1.0 + TIE))
+        best = _pick(timings)
+        timings_c[c] = list(timings)
         wpm[c] = best[0]
         pipe_c[c] = best[1]
         ovl_c[c] = best[3]
         pack_c[c] = best[5]
-        if best[3]:
-            ovl_at_g[c] = {G: min((x for x in ovl if x[2] == G), key=lambda x: x[4])[3]
-                           for G in sorted({x[2] for x in ovl})}
         # runners-up for the whole-ensemble stage: the class's other schedules within
         # RUNNER_UP of its fastest, fastest first (one per kind of schedule)
         seen = {(best[0], best[1], best[3], best[5])}
@@ -194,24 +202,31 @@ def tune(descs, seed=0, S_probe=None, min_markets=None, cache=None, arch="gfx950
         cost[c] = best[4] * 1e6 / (len(probe) * Sp) * ncu
         cached[key] = {"waves_per_market": wpm[c], "pipelined": bool(pipe_c[c]), "overlap": ovl_c[c],
                        "pack": pack_c[c], "ns_per_market_step": cost[c]}
-    # waves per workgroup on the whole ensemble; classes that asked for more waves per market
-    # than a candidate group holds are clamped to it
-    # (an overlapped class runs, at each candidate, the clearing share that was fastest at
-    # that workgroup size in its own probe, if it was probed there)
+    # waves per workgroup on the whole ensemble: at each candidate size every class runs the
+    # fastest of its probed schedules that fits a workgroup of that size (classes taken from
+    # the cache are clamped to it)
+    def fitting(c, G):
+        if c in timings_c:
+            fit = [x for x in timings_c[c] if x[0] <= G and (not x[1] or x[2] == G)]
+            if fit:
+                x = _pick(fit)
+                return x[0], x[1], x[3], x[5]
+        return min(wpm[c], G), pipe_c[c] and G >= 2, ovl_c.get(c, 0), pack_c[c]
+
     best_g = None
     for G in GROUP_CANDIDATES:
-        ovl_g = {c: ovl_at_g.get(c, {}).get(G, k) for c, k in ovl_c.items() if k}
-        tn = {"waves_per_group": G, "waves_per_market": {int(c): min(w, G) for c, w in wpm.items()},
-              "pipelined": {int(c): 1 for c, p in pipe_c.items() if p},
-              "overlap": {int(c): k for c, k in ovl_g.items()},
-              "pack": {int(c): P for c, P in pack_c.items() if P}}
+        sel = {c: fitting(c, G) for c in wpm}
+        tn = {"waves_per_group": G, "waves_per_market": {int(c): v[0] for c, v in sel.items()},
+              "pipelined": {int(c): 1 for c, v in sel.items() if v[1]},
+              "overlap": {int(c): v[2] for c, v in sel.items() if v[2]},
+              "pack": {int(c): v[3] for c, v in sel.items() if v[3]}}
         ms = _time_launch(descs, seed, tn, S_probe or probe_steps(descs))
         if log:
             log("waves_per_group %2d: %.3f ms" % (G, ms))
         if best_g is None or ms < best_g[1]:
-            best_g = (G, ms, ovl_g)
-    wpm = {c: min(w, best_g[0]) for c, w in wpm.items()}
-    ovl_c.update(best_g[2])
+            best_g = (G, ms, sel)
+    for c, v in best_g[2].items():
+        wpm[c], pipe_c[c], ovl_c[c], pack_c[c] = v
     # whole-ensemble stage: a class's own probe fills the GPU with that class alone, while in a
     # small mixed ensemble its markets share the chip with the others and the longest chains of
     # steps set the launch's end.  For the classes that carry most of the events, each runner-up
