@@ -40,6 +40,8 @@ enum Kind : int {
     K_GEN_NOISE = 12,
     K_LDS_RW_B64 = 13,
     K_GEN_NOISE4 = 14,
+    K_ADD_SMUL = 15,  // v_add_u32 and s_mul_i32 alternating, eight independent chains of each
+    K_SMUL = 16,      // s_mul_i32 alone
 };
 
 // Shader-clock cycles and 100 MHz real-time ticks of the timed loop, per workgroup.
@@ -69,6 +71,10 @@ __global__ void __launch_bounds__(1024) ub_valu(uint32_t *out, uint64_t *clk, ui
     }
     const float fb = 0.999f;
     const double gb = 0.999;
+    uint32_t sc[8];
+    const uint32_t sb = (uint32_t)__builtin_amdgcn_readfirstlane((int)(b | 1u));
+#pragma unroll
+    for (int j = 0; j < 8; ++j) sc[j] = (uint32_t)__builtin_amdgcn_readfirstlane((int)(blockIdx.x + 3u * (uint32_t)j));
     __syncthreads();
     uint64_t c0, r0, c1, r1;
     stamp(clk, c0, r0);
@@ -92,6 +98,12 @@ __global__ void __launch_bounds__(1024) ub_valu(uint32_t *out, uint64_t *clk, ui
                 asm volatile("v_fma_f32 %0, %0, %1, %1" : "+v"(f[j]) : "v"(fb));
             } else if constexpr (KIND == K_FMA_F64) {
                 asm volatile("v_fma_f64 %0, %0, %1, %1" : "+v"(g[j]) : "v"(gb));
+            } else if constexpr (KIND == K_ADD_SMUL) {
+                // scalar products leave SCC alone, so the loop's own compare is undisturbed
+                asm volatile("v_add_u32 %0, %0, %1" : "+v"(a[j]) : "v"(b));
+                asm volatile("s_mul_i32 %0, %0, %1" : "+s"(sc[j]) : "s"(sb));
+            } else if constexpr (KIND == K_SMUL) {
+                asm volatile("s_mul_i32 %0, %0, %1" : "+s"(sc[j]) : "s"(sb));
             }
         }
     }
@@ -100,7 +112,7 @@ __global__ void __launch_bounds__(1024) ub_valu(uint32_t *out, uint64_t *clk, ui
     uint32_t r = 0;
 #pragma unroll
     for (int j = 0; j < 8; ++j)
-        r ^= a[j] ^ (uint32_t)p[j] ^ (uint32_t)(p[j] >> 32) ^ (uint32_t)f[j] ^ (uint32_t)g[j];
+        r ^= a[j] ^ (uint32_t)p[j] ^ (uint32_t)(p[j] >> 32) ^ (uint32_t)f[j] ^ (uint32_t)g[j] ^ sc[j];
     out[blockIdx.x * blockDim.x + threadIdx.x] = r;
     if (threadIdx.x == 0) {
         clk[2 * blockIdx.x] = c1 - c0;
@@ -323,6 +335,8 @@ int cae_ubench_run(int kind, uint32_t blocks, uint32_t threads, uint32_t iters, 
     case K_LDS_ADD_WINDOW: hipLaunchKernelGGL(ub_lds<K_LDS_ADD_WINDOW>, g, b, 0, nullptr, out, clk, iters, 1u); break;
     case K_FMA_F32: hipLaunchKernelGGL(ub_valu<K_FMA_F32>, g, b, 0, nullptr, out, clk, iters, 1u); break;
     case K_FMA_F64: hipLaunchKernelGGL(ub_valu<K_FMA_F64>, g, b, 0, nullptr, out, clk, iters, 1u); break;
+    case K_ADD_SMUL: hipLaunchKernelGGL(ub_valu<K_ADD_SMUL>, g, b, 0, nullptr, out, clk, iters, 1u); break;
+    case K_SMUL: hipLaunchKernelGGL(ub_valu<K_SMUL>, g, b, 0, nullptr, out, clk, iters, 1u); break;
     case K_LDS_RW_B64: hipLaunchKernelGGL(ub_lds_rw, g, b, 0, nullptr, out, clk, iters, 1u); break;
     case K_MAD_U64_CONST: hipLaunchKernelGGL(ub_mad_const, g, b, 0, nullptr, out, clk, iters, kM0); break;
     case K_PHILOX_ROUNDS: hipLaunchKernelGGL(ub_philox_rounds, g, b, 0, nullptr, out, clk, iters, 1u, 2u); break;

@@ -26,7 +26,7 @@ KINDS = {"v_add_u32": 0, "v_xor_b32": 1, "v_bitop3_b32": 2, "v_mul_hi_u32": 3,
          "v_mul_lo_u32": 4, "v_mad_u64_u32": 5, "ds_add_u32_conflict_free": 6,
          "ds_add_u32_window66": 7, "v_fma_f32": 8, "v_fma_f64": 9,
          "mad_u64_const": 10, "philox_rounds": 11, "gen_noise_events": 12, "ds_rw_b64_words": 13,
-         "gen_noise_events_4rows": 14}
+         "gen_noise_events_4rows": 14, "v_add_u32_with_s_mul_i32": 15, "s_mul_i32": 16}
 # operations per lane and loop iteration of each kernel
 OPS_PER_ITER = {k: 8 for k in KINDS}
 OPS_PER_ITER.update({"philox_rounds": 80, "gen_noise_events": 2, "ds_rw_b64_words": 16,
@@ -103,6 +103,12 @@ def summary(res, nw=16):
            "lds_conflict_free_lane_atomics_per_clk_cu": 64.0 * g("ds_add_u32_conflict_free"),
            "lds_rw_b64_lane_words_per_clk_cu": 64.0 * g("ds_rw_b64_words"),
            "ghz": res["v_add_u32@%dw" % nw]["ghz"]}
+    # one wave per SIMD (4 waves per CU): what a single wave can issue per SIMD clock, VALU alone,
+    # VALU with one scalar instruction after each, and scalar alone
+    one = lambda k: res["%s@4w" % k]["cu_ipc"] / 4.0
+    out["one_wave_valu_per_simd_clk"] = one("v_add_u32")
+    out["one_wave_valu_per_simd_clk_with_salu"] = one("v_add_u32_with_s_mul_i32")
+    out["one_wave_salu_per_simd_clk"] = one("s_mul_i32")
     return out
 
 
