@@ -151,6 +151,16 @@ struct ClearOut {
 // numbers as b - (min(D(q), V*) - min(D(q+1), V*)) and its ask counterpart, with fewer steps.
 __device__ __forceinline__ uint32_t unmatched(uint32_t x, uint32_t v) { return __builtin_elementwise_sub_sat(x, v); }
 
+// min(x, 1) in one instruction, for counting ticks with a positive unmatched quantity.  Written
+// out because the compiler's own form of the count (a compare and a carry-add per tick) puts
+// every tick on the condition register, one after another with wait states between them.
+__device__ __forceinline__ uint32_t nonzero(uint32_t x)
+{
+    uint32_t r;
+    asm("v_min_u32 %0, 1, %1" : "=v"(r) : "v"(x));
+    return r;
+}
+
 // Reads / writes CH consecutive (bid, ask) pairs starting at tick q of an LDS book.
 template <int CH>
 __device__ __forceinline__ void load_pairs(const uint32_t *bk, uint32_t q, uint32_t (&b)[CH], uint32_t (&k)[CH])
@@ -239,27 +249,28 @@ __device__ __forceinline__ ClearOut clear_small(uint32_t *__restrict__ bk, uint3
         for (int j = 0; j < TPL; ++j) pj += Sq[j] < vs ? 1u : 0u;
         out.p = readlane(pj, crossing_lane(Sq[TPL - 1] >= vs));
     }
+    // Best quotes after the fill, from the curves: the unmatched demand max(D(q) - V*, 0) falls
+    // with q and the residual bids are its drops, so the best bid is the highest tick with
+    // D > V*; likewise the best ask is the lowest tick with S > V*.  The ticks with D > V* are a
+    // prefix of the book (the last lane whose first tick is in it holds the best bid), those
+    // with S <= V* too (the first lane whose top tick is past it holds the best ask).
     uint32_t ud = unmatched(D[0], vs), us = unmatched(Sb, vs);
+    uint32_t nb = q0 - 1u, ns = 0;
 #pragma unroll
     for (int j = 0; j < TPL; ++j) {
         const uint32_t ud1 = unmatched(D[j + 1], vs), us1 = unmatched(Sq[j], vs);
+        nb += nonzero(ud);
+        ns += nonzero(us1);
         b[j] = ud - ud1;
         k[j] = us1 - us;
         ud = ud1;
         us = us1;
     }
     store_pairs<TPL>(bk, q0, b, k);
-    uint32_t hb = kNone, la = kNone;
-#pragma unroll
-    for (int j = 0; j < TPL; ++j)
-        if (b[j] != 0) hb = q0 + j;
-#pragma unroll
-    for (int j = TPL - 1; j >= 0; --j)
-        if (k[j] != 0) la = q0 + j;
-    const uint64_t mb = ballot(hb != kNone);
-    const uint64_t ma = ballot(la != kNone);
-    out.bb = mb ? readlane(hb, 63u - (uint32_t)__builtin_clzll(mb)) : kNone;
-    out.ba = ma ? readlane(la, (uint32_t)__builtin_ctzll(ma)) : kNone;
+    const uint64_t mb = ballot(D[0] > vs);
+    const uint64_t ma = ballot(Sq[TPL - 1] > vs);
+    out.bb = mb ? readlane(nb, 63u - (uint32_t)__builtin_clzll(mb)) : kNone;
+    out.ba = ma ? readlane(q0 + TPL - ns, (uint32_t)__builtin_ctzll(ma)) : kNone;
     return out;
 }
 
@@ -315,7 +326,9 @@ __device__ __forceinline__ ClearOut clear_wave(uint32_t *__restrict__ bk, uint32
     // closed-form price-priority fill (all zero when V* = 0), then best bid / best ask; the
     // clearing tick is the lowest tick with S >= V*
     const uint32_t vs = out.v;
-    uint32_t hb = kNone, la = kNone, pj = q0;
+    // best quotes after the fill as in clear_small: the best bid is the highest tick with
+    // D > V*, the best ask the lowest tick with S > V*
+    uint32_t nb = q0 - 1u, na = q0 + TPL, pj = q0;
     {
         uint32_t cb = eb, ca = ea;
 #pragma unroll 2
@@ -335,18 +348,18 @@ __device__ __forceinline__ ClearOut clear_wave(uint32_t *__restrict__ bk, uint32
                 b[j] -= fb;
                 k[j] -= fs;
                 pj += Sq < vs ? 1u : 0u;
+                nb += nonzero(unmatched(D, vs));
+                na -= nonzero(unmatched(Sq, vs));
                 changed |= (fb | fs) != 0;
-                if (b[j] != 0) hb = qc + j;
-                if (k[j] != 0 && la == kNone) la = qc + j;
             }
             if (changed) store_pairs<CH>(bk, qc, b, k);
         }
     }
     out.p = readlane(pj, crossing_lane(ia >= vs));
-    const uint64_t mb = ballot(hb != kNone);
-    const uint64_t ma = ballot(la != kNone);
-    out.bb = mb ? readlane(hb, 63u - (uint32_t)__builtin_clzll(mb)) : kNone;
-    out.ba = ma ? readlane(la, (uint32_t)__builtin_ctzll(ma)) : kNone;
+    const uint64_t mb = ballot(Tb - eb > vs);  // D of the lane's first tick
+    const uint64_t ma = ballot(ia > vs);       // S of the lane's top tick
+    out.bb = mb ? readlane(nb, 63u - (uint32_t)__builtin_clzll(mb)) : kNone;
+    out.ba = ma ? readlane(na, (uint32_t)__builtin_ctzll(ma)) : kNone;
     return out;
 }
 
@@ -655,6 +668,59 @@ __device__ __forceinline__ void flush_rel(const DevMarket &d, uint32_t last, uin
         if (j0 + lane < span + 2u) P[j0 + lane] = make_uint2(0u, 0u);
 }
 
+// The same flush when the bins fit one pass (2K + 5 <= 64 lanes), with each lane's role fixed
+// for the market: the pair it reads, its tick relative to the reference, and masks that pick
+// which bin words go to the bid and to the ask.  Only the momentum lanes' masks depend on the
+// step (through the trend), so a step's flush is a few masks, one read, one 64-bit add and the
+// bins' reset, without branches.
+struct FlushLanes {
+    uint32_t pj;        // bin pair the lane reads
+    int dt;             // its tick relative to the reference
+    uint32_t bx, ay;    // ~0: the pair's bid word goes to the bid / its ask word to the ask
+    uint32_t mb, ms;    // ~0: the momentum-buy lane / the momentum-sell lane
+};
+
+// A per-lane value the compiler must keep as a vector word (it would otherwise turn the masks
+// into lane masks held in scalar registers, which the step loop cannot spare).
+__device__ __forceinline__ uint32_t vword(uint32_t x)
+{
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
+__device__ __forceinline__ FlushLanes flush_lanes(const DevMarket &d, uint32_t lane)
+{
+    const uint32_t span = 2u * d.K + 1u;
+    const uint32_t e = lane - span;  // 0..3 for the momentum and maker lanes
+    const bool noise = lane < span;
+    FlushLanes f;
+    f.pj = noise ? lane : span + min(e >> 1, 1u);
+    // lanes past the four momentum and maker lanes add zero at distinct ticks (no collisions)
+    f.dt = (noise || e > 3u) ? (int)lane - (int)d.K
+                              : (e == 0u ? 1 : (e == 1u ? -1 : (e == 2u ? -(int)d.h : (int)d.h)));
+    f.bx = vword((noise || e == 2u) ? ~0u : 0u);
+    f.ay = vword((noise || e == 3u) ? ~0u : 0u);
+    f.mb = vword((!noise && e == 0u) ? ~0u : 0u);
+    f.ms = vword((!noise && e == 1u) ? ~0u : 0u);
+    return f;
+}
+
+__device__ __forceinline__ void flush_rel_lanes(const FlushLanes &f, uint32_t span, int top, uint32_t last,
+                                                uint32_t prev, uint32_t *H, uint32_t *bk, uint32_t lane)
+{
+    const uint32_t up = last > prev ? ~0u : 0u, dn = last < prev ? ~0u : 0u, flat = last == prev ? ~0u : 0u;
+    uint2 *P = reinterpret_cast<uint2 *>(H);
+    const uint2 v = P[f.pj];
+    // momentum buys take both coins' quantities when the trend is up, the coin's buys when it is
+    // flat; sells alike
+    const uint32_t lo = (v.x & (f.bx | (f.mb & (up | flat)))) + (v.y & f.mb & up);
+    const uint32_t hi = (v.x & f.ms & dn) + (v.y & (f.ay | (f.ms & (dn | flat))));
+    const int tick = clamp_tick((int)last + f.dt, top);
+    atomicAdd(reinterpret_cast<unsigned long long *>(bk) + tick, ((unsigned long long)hi << 32) | lo);
+    // after the reads (one wave's LDS accesses execute in order)
+    if (lane < span + 2u) P[lane] = make_uint2(0u, 0u);
+}
+
 // Mid-price orders of step s aggregated before the reference 2 mid = 2n + e is known.  A NOISE
 // order's tick floor(mid + K (2 w1 / 2^32 - 1) + 1/2) is n - K + g + c for e = 0 and
 // n - K + g + 1 for e = 1, with g = hi(2K w1) and c = [lo(2K w1) >= 2^31]; it is binned by
@@ -851,24 +917,21 @@ __device__ __forceinline__ void run_market(const EngineArgs &args, const Item &i
     if constexpr (FULL && MULTI) __syncthreads();  // every wave has read the book before orders land
 
     const double *lnT = args.lnT + d.L;  // ln(L + tick)
-    // The log return of step i is added after step i + 1's orders are generated, so the table
-    // load issued after the clearing has long returned when it is used (same values, same order
-    // of the floating-point sums).  ln_last = ln(L + last) of the step before.
-    double ln_last = 0.0, ln_new = 0.0;
+    // The log return of step i is added at the end of step i + 1: the table load for the price
+    // step i set is issued when step i + 1 starts and has long returned after its orders and
+    // clearing (same values, same order of the floating-point sums).  ln_prev = ln(L + price)
+    // before step i.
+    double ln_prev = 0.0;
     if constexpr (!kLazy) {
-        if (active) ln_last = lnT[last];
+        if (active) ln_prev = lnT[last];
     }
     for (uint32_t i = 0; i < args.S; ++i) {
         const uint32_t s = (uint32_t)steps0 + i;
-        if (active) gen_orders<FULL>(d, d.id, s, Refs{last, prev, mid2, mid2p}, args.k0, args.k1, t, nthr, bk);
+        double ln_cur = 0.0;
         if constexpr (!kLazy) {
-            if (active && i >= 1u) {
-                const double r = ln_new - ln_last;
-                sum_r = sum_r + r;
-                sum_r2 = sum_r2 + r * r;
-                ln_last = ln_new;
-            }
+            if (active && i >= 1u) ln_cur = lnT[last];
         }
+        if (active) gen_orders<FULL>(d, d.id, s, Refs{last, prev, mid2, mid2p}, args.k0, args.k1, t, nthr, bk);
         if constexpr (MULTI) __syncthreads();
         else wave_sync();
         ClearOut co;
@@ -908,7 +971,12 @@ __device__ __forceinline__ void run_market(const EngineArgs &args, const Item &i
                     sum_spread += (uint64_t)(co.ba - co.bb);
                     n_spread += 1;
                 }
-                ln_new = lnT[last];  // this step's return is added during the next step
+                if (i >= 1u) {  // the previous step's return
+                    const double r = ln_cur - ln_prev;
+                    sum_r = sum_r + r;
+                    sum_r2 = sum_r2 + r * r;
+                    ln_prev = ln_cur;
+                }
             }
             mid2p = mid2;
             mid2 = next_mid2(mid, co.bb, co.ba, last);
@@ -919,7 +987,7 @@ __device__ __forceinline__ void run_market(const EngineArgs &args, const Item &i
     }
     if constexpr (!kLazy) {
         if (active && args.S >= 1u) {  // the last step's log return
-            const double r = ln_new - ln_last;
+            const double r = lnT[last] - ln_prev;
             sum_r = sum_r + r;
             sum_r2 = sum_r2 + r * r;
         }
@@ -1032,6 +1100,10 @@ __device__ __forceinline__ void run_market_ovl(const EngineArgs &args, const Ite
     uint64_t n_trade = 0, sum_vol = 0, sum_px = 0, sum_spread = 0, n_spread = 0;  // this wave's steps
     const uint32_t own = min(d.A, item.share * 64u);        // agents of the clearing wave
     const uint32_t ostride = nthr - 64u;                   // the other waves' stride
+    const uint32_t span = 2u * d.K + 1u;
+    const int top = (int)d.L - 1;
+    const bool one_pass = span + 4u <= 64u;
+    const FlushLanes fl = flush_lanes(d, lane);
     for (uint32_t i = 0; i < args.S; ++i) {
         const uint32_t s = (uint32_t)steps0 + i;
         const uint32_t c = (i >> kOvlBlockLog2) & wpm_mask;
@@ -1047,7 +1119,10 @@ __device__ __forceinline__ void run_market_ovl(const EngineArgs &args, const Ite
                 sum_r = fs[0];
                 sum_r2 = fs[1];
             }
-            if (i >= 1u) flush_rel(d, last, prev, (i & 1u) ? H1 : H0, bk, lane);
+            if (i >= 1u) {
+                if (one_pass) flush_rel_lanes(fl, span, top, last, prev, (i & 1u) ? H1 : H0, bk, lane);
+                else flush_rel(d, last, prev, (i & 1u) ? H1 : H0, bk, lane);
+            }
             wave_sync();
             const ClearOut co = clear_dispatch<TPL_MAX>(bk, d.tpl, lane);
             if (co.v != 0) {
@@ -1625,20 +1700,11 @@ __device__ __forceinline__ uint32_t row_max(uint32_t x)
     return row_last(x);
 }
 
-__device__ __forceinline__ uint32_t row_min(uint32_t x)
-{
-    x = min(x, dpp_or<0x111>(kNone, x));
-    x = min(x, dpp_or<0x112>(kNone, x));
-    x = min(x, dpp_or<0x114>(kNone, x));
-    x = min(x, dpp_or<0x118>(kNone, x));
-    return row_last(x);
-}
-
 // One clearing pass over the book of each 16-lane segment (four books per wave), TPL ticks per
 // lane (ll: the lane's index in its segment; wr: the segment holds a market).  By the definitions:
 // V* = max over ticks of min(D, S) (a row maximum of the lanes' maxima); since S rises with the
 // tick, the lowest tick with V = V* is the number of ticks with S < V* (a row sum); the best
-// quotes after the fill are a row maximum and minimum.  D and S of each tick are re-formed by
+// quotes after the fill are counts of ticks too, summed with it.  D and S of each tick are re-formed by
 // running sums in every pass, so only the book words stay live.  Segment-uniform result.
 template <int TPL>
 __device__ __forceinline__ ClearOut clear_row(uint32_t *__restrict__ bk, uint32_t ll, bool wr)
@@ -1666,16 +1732,19 @@ __device__ __forceinline__ ClearOut clear_row(uint32_t *__restrict__ bk, uint32_
     ClearOut out;
     out.v = row_max(mv);
     const uint32_t vs = out.v;
+    uint32_t cp = 0;  // ticks with S < V*: the clearing tick is their number
     {
-        uint32_t cnt = 0, t = Sb;
+        uint32_t t = Sb;
 #pragma unroll
         for (int j = 0; j < TPL; ++j) {
             t += k[j];
-            cnt += t < vs ? 1u : 0u;
+            cp += nonzero(unmatched(vs, t));
         }
-        out.p = row_sum(cnt);
     }
-    uint32_t ud = unmatched(D0, vs), us = unmatched(Sb, vs);
+    // the fill, counting the ticks with D > V* (the best bid after the fill is the highest such
+    // tick: the unmatched demand max(D - V*, 0) falls with the tick and the residual bids are
+    // its drops) and with S > V* (the best ask is the lowest such tick)
+    uint32_t ud = unmatched(D0, vs), us = unmatched(Sb, vs), cb = 0, cs = 0;
     d = D0;
     sq = Sb;
 #pragma unroll
@@ -1683,21 +1752,20 @@ __device__ __forceinline__ ClearOut clear_row(uint32_t *__restrict__ bk, uint32_
         d -= b[j];
         sq += k[j];
         const uint32_t ud1 = unmatched(d, vs), us1 = unmatched(sq, vs);
+        cb += nonzero(ud);
+        cs += nonzero(us1);
         b[j] = ud - ud1;
         k[j] = us1 - us;
         ud = ud1;
         us = us1;
     }
     if (wr) store_pairs<TPL>(bk, q0, b, k);
-    uint32_t hb = kNone, la = kNone;
-#pragma unroll
-    for (int j = 0; j < TPL; ++j)
-        if (b[j] != 0) hb = q0 + j;
-#pragma unroll
-    for (int j = TPL - 1; j >= 0; --j)
-        if (k[j] != 0) la = q0 + j;
-    out.bb = row_max(hb + 1u) - 1u;  // kNone + 1 = 0: a row without bids gives kNone back
-    out.ba = row_min(la);
+    // the three counts in one row sum, in 10-bit fields (a row has at most 16 TPL = 128 ticks)
+    const uint32_t tot = row_sum(cp | (cb << 10) | (cs << 20));
+    out.p = tot & 1023u;
+    out.bb = ((tot >> 10) & 1023u) - 1u;  // no tick: kNone
+    const uint32_t nsa = tot >> 20;       // ticks with S > V*, the top of the row's ticks
+    out.ba = nsa ? 16u * TPL - nsa : kNone;
     return out;
 }
 
@@ -1760,11 +1828,12 @@ __device__ __forceinline__ void run_packed_seg(const EngineArgs &args, const Ite
     wave_sync();
     const double *lnT = args.lnT + d.L;  // ln(L + tick)
     const uint32_t A = active ? d.A : 0u;
-    // each step's log return is added after the next step's orders (the table load is then long
-    // back); ln_last = ln(L + last) of the step before
-    double ln_last = active ? lnT[last] : 0.0, ln_new = 0.0;
+    // each step's log return is added at the end of the next step, whose start issues the table
+    // load (long back by then); ln_prev = ln(L + price) before the step whose return is pending
+    double ln_prev = active ? lnT[last] : 0.0;
     for (uint32_t i = 0; i < args.S; ++i) {
         const uint32_t s = s0 + i;
+        const double ln_cur = (active && i >= 1u) ? lnT[last] : 0.0;
         {
             const OrderCtx o = order_ctx<false>(d, s, Refs{last, prev, 2u * last, 0u});
             const PhiloxStep gen(s, d.id, args.k0, args.k1);
@@ -1781,12 +1850,6 @@ __device__ __forceinline__ void run_packed_seg(const EngineArgs &args, const Ite
                     atomicAdd(&bk[w], order_qty(o, w2));
                 }
             }
-        }
-        if (active && i >= 1u) {
-            const double r = ln_new - ln_last;
-            sum_r = sum_r + r;
-            sum_r2 = sum_r2 + r * r;
-            ln_last = ln_new;
         }
         wave_sync();
         // a segment without a market reads slot 0's book (its lanes point there) but writes
@@ -1806,7 +1869,12 @@ __device__ __forceinline__ void run_packed_seg(const EngineArgs &args, const Ite
                     atomicAdd(reinterpret_cast<unsigned long long *>(acc + 4), 1ull);
                 }
             }
-            ln_new = lnT[last];
+            if (i >= 1u) {  // the previous step's return
+                const double r = ln_cur - ln_prev;
+                sum_r = sum_r + r;
+                sum_r2 = sum_r2 + r * r;
+                ln_prev = ln_cur;
+            }
             if constexpr (TRACE) {
                 if (ll == 0) trace_step(args, m, i, last, co.v);
             }
@@ -1814,7 +1882,7 @@ __device__ __forceinline__ void run_packed_seg(const EngineArgs &args, const Ite
         wave_sync();
     }
     if (active && args.S >= 1u) {  // the last step's log return
-        const double r = ln_new - ln_last;
+        const double r = lnT[last] - ln_prev;
         sum_r = sum_r + r;
         sum_r2 = sum_r2 + r * r;
     }
