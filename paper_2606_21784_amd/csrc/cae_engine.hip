@@ -1098,6 +1098,11 @@ __device__ __forceinline__ void run_market_ovl(const EngineArgs &args, const Ite
 
     const double *lnT = args.lnT + d.L;
     uint64_t n_trade = 0, sum_vol = 0, sum_px = 0, sum_spread = 0, n_spread = 0;  // this wave's steps
+    // the statistics of the steps of the current block, in 32 bits: its volumes sum to at most
+    // the shares ever added to the book (below 2^32 by the host guard), its ticks and spreads to
+    // at most kOvlBlock (L - 1)
+    uint32_t b_trade = 0, b_vol = 0, b_px = 0, b_spread = 0, b_nspread = 0;
+    double ln_cur = 0.0;  // ln(L + last) on the clearing wave
     const uint32_t own = min(d.A, item.share * 64u);        // agents of the clearing wave
     const uint32_t ostride = nthr - 64u;                   // the other waves' stride
     const uint32_t span = 2u * d.K + 1u;
@@ -1119,38 +1124,45 @@ __device__ __forceinline__ void run_market_ovl(const EngineArgs &args, const Ite
                 sum_r = fs[0];
                 sum_r2 = fs[1];
             }
+            if ((i & (kOvlBlock - 1u)) == 0u) ln_cur = lnT[last];  // used after this step's rows
             if (i >= 1u) {
                 if (one_pass) flush_rel_lanes(fl, span, top, last, prev, (i & 1u) ? H1 : H0, bk, lane);
                 else flush_rel(d, last, prev, (i & 1u) ? H1 : H0, bk, lane);
             }
             wave_sync();
             const ClearOut co = clear_dispatch<TPL_MAX>(bk, d.tpl, lane);
-            if (co.v != 0) {
-                n_trade += 1;
-                sum_vol += co.v;
-                sum_px += co.p;
-            }
-            if (co.bb != kNone && co.ba != kNone) {
-                sum_spread += (uint64_t)(co.ba - co.bb);
-                n_spread += 1;
-            }
+            const bool traded = co.v != 0;
+            const bool quoted = co.bb != kNone && co.ba != kNone;
+            b_trade += traded ? 1u : 0u;
+            b_vol += co.v;
+            b_px += traded ? co.p : 0u;
+            b_spread += quoted ? co.ba - co.bb : 0u;
+            b_nspread += quoted ? 1u : 0u;
             ref2 = 2u * last;
             prev = last;
-            if (co.v != 0) last = co.p;
+            if (traded) last = co.p;
             if constexpr (TRACE) {
                 if (lane == 0) trace_step(args, m, i, last, co.v);
             }
-            // the log-table loads are issued here and consumed after the wave's rows
-            const double x = lnT[last] - lnT[prev];
+            // the log-table load is issued here and consumed after the wave's rows
+            const double ln_new = lnT[last];
             if (more) gen_rel(d, s + 1u, PhiloxStep(s + 1u, d.id, args.k0, args.k1), 0u, 64u, own, lane, Hn);
+            const double x = ln_new - ln_cur;
             sum_r = sum_r + x;
             sum_r2 = sum_r2 + x * x;
+            ln_cur = ln_new;
             if (((i + 1u) & (kOvlBlock - 1u)) == 0u || !more) {  // hand over (or finish)
                 if (lane == 0) {
                     *reinterpret_cast<uint4 *>(scr) = make_uint4(last, prev, ref2, 0u);
                     fs[0] = sum_r;
                     fs[1] = sum_r2;
                 }
+                n_trade += b_trade;
+                sum_vol += b_vol;
+                sum_px += b_px;
+                sum_spread += b_spread;
+                n_spread += b_nspread;
+                b_trade = b_vol = b_px = b_spread = b_nspread = 0u;
             }
             __builtin_amdgcn_s_setprio(0);
         } else if (active && more) {
