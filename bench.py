@@ -448,6 +448,10 @@ def main():
                     help="file for every leg's full detail (JSON)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="after timing, copy 1 GiB device-to-device (counter calibration)")
+    ap.add_argument("--schedule", default=None,
+                    help="run the headline in this schedule instead of the autotuner's: "
+                         "waves_per_group,waves_per_market,overlap (e.g. 8,4,4), so that separate "
+                         "profiler passes all time the same code")
     ap.add_argument("--steps-per-call", type=int, default=0,
                     help="auction steps per launch instead of the workload's 1000 (for the HBM "
                          "check that traffic does not grow with S; the result line then names "
@@ -475,14 +479,19 @@ def main():
     events = float(np.sum(d["A"].astype(np.float64))) * S
     from paper_2606_21784_amd import autotune
     t0 = time.perf_counter()
-    tn = autotune.tune(d, seed=w["seed"], log=log if VERBOSE else None)
+    if args.schedule:
+        g, wpm, ovl = (int(x) for x in args.schedule.split(","))
+        c = int(autotune.classes_of(d)[0])  # the fixed workload is one size class
+        tn = {"waves_per_group": g, "waves_per_market": {c: wpm}, "overlap": {c: ovl} if ovl else {}}
+    else:
+        tn = autotune.tune(d, seed=w["seed"], log=log if VERBOSE else None)
     tune_s = time.perf_counter() - t0
     ens = engine.Ensemble(d, w["seed"], tuning=tn)
     sched = ens.tuning()
     sched = {"waves_per_group": sched["waves_per_group"], "groups_per_cu": sched["groups_per_cu"],
              "waves_per_market": sorted(set(sched["waves_per_market"].values())),
              "pipelined": bool(sched["pipelined"]), "overlap": sorted(set(sched["overlap"].values())),
-             "autotune_s": round(tune_s, 2)}
+             "autotune_s": round(tune_s, 2), "pinned": bool(args.schedule)}
     log("schedule:", json.dumps(sched))
 
     first_bk = None  # books after the first launch, checked against the oracle below
