@@ -68,6 +68,26 @@ def test_exhaustive_small_books(orc, L):
             assert ps[i] == 0
         assert res[i, 0].tolist() == nb.tolist(), (bid, ask)
         assert res[i, 1].tolist() == na.tolist(), (bid, ask)
+        D = [sum(bid[q:]) for q in range(L)]
+        S = [sum(ask[:q + 1]) for q in range(L)]
+        _check_best_quotes(D, S, k, res[i, 0], res[i, 1])
+
+
+def _check_best_quotes(D, S, v, nb, na):
+    """The best quotes after the fill follow from the curves alone: the unmatched demand
+    max(D(q) - V*, 0) falls with q and the residual bids are its drops, so the best bid is the
+    highest tick with D > V*; the best ask is the lowest tick with S > V*.  (The engine's
+    clearing takes them as these counts of ticks instead of scanning the residual.)"""
+    D = np.asarray(D, np.int64)
+    S = np.asarray(S, np.int64)
+    L = len(D)
+    hb = np.nonzero(np.asarray(nb))[0]
+    la = np.nonzero(np.asarray(na))[0]
+    nd = int(np.sum(D > v))  # the ticks with D > V* are a prefix of the book
+    ns = int(np.sum(S <= v))  # the ticks with S <= V* too
+    assert np.all(D[:nd] > v) and np.all(S[:ns] <= v)
+    assert (hb.max() if len(hb) else None) == (nd - 1 if nd else None)
+    assert (la.min() if len(la) else None) == (ns if ns < L else None)
 
 
 def _check_invariants(bid, ask, p, v, nb, na):
@@ -95,6 +115,7 @@ def _check_invariants(bid, ask, p, v, nb, na):
     la = np.nonzero(na)[0]
     if len(hb) and len(la):
         assert hb.max() < la.min()
+    _check_best_quotes(D, S, v, nb, na)
     # price priority: a bid level is touched only if every better level is fully filled
     for q in range(L):
         if fb[q] > 0:
