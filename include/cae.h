@@ -141,7 +141,12 @@ typedef struct cae_tuning {
     uint32_t waves_per_group;                   /* waves per workgroup (1..16)           */
     uint32_t groups_per_cu;                     /* resident workgroups per CU to launch   */
     uint32_t max_lds_bytes;                     /* LDS budget per workgroup               */
-    uint32_t flags;                             /* bit 0: keep descriptor order (no LPT)  */
+    uint32_t flags;                             /* bit 0: keep descriptor order (no LPT);
+                                                   bit 1: in an ensemble whose work items
+                                                   differ in cost per step, the waves of the
+                                                   items within a quarter of the costliest
+                                                   (lock-step or single-wave markets) issue
+                                                   one priority level above the others'     */
     uint8_t waves_per_market[CAE_NUM_CLASSES];  /* 1,2,4,8,16 per size class; 0 = auto    */
     uint8_t pipelined[CAE_NUM_CLASSES];         /* 1: markets of this class run in pairs
                                                    that share all waves_per_group waves in

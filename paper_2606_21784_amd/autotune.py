@@ -13,7 +13,9 @@ The engine's schedule has these knobs (``cae_tuning`` in include/cae.h):
   * waves per workgroup: how many markets of one class share a workgroup (in lock-step when a
     market spans more than one wave) and therefore how the workgroup's LDS is partitioned into
     market slices;
-  * the resident workgroups per CU that the persistent grid is sized for.
+  * the resident workgroups per CU that the persistent grid is sized for;
+  * a priority boost (tuning flag bit 1): in a mixed ensemble the waves of the costliest
+    markets, which hold the launch's critical path, issue one priority level above the rest.
 
 ``tune`` times candidates on the GPU through the C ABI (short launches on copies of the
 ensemble's own markets), keeps the fastest per class, then picks waves-per-workgroup on the
@@ -40,6 +42,8 @@ TIE = 0.02
 HEAVY_SHARE, MAX_HEAVY, MAX_RUNNERS, RUNNER_UP = 0.1, 4, 3, 0.25
 # The overlapped schedule is also probed at the second fastest plain width within this fraction.
 OVL_SECOND = 0.3
+# cae_tuning flag: the costliest markets' waves issue one priority level above the others'.
+BOOST = 2
 
 
 def classes_of(descs):
@@ -260,6 +264,18 @@ def tune(descs, seed=0, S_probe=None, min_markets=None, cache=None, arch="gfx950
                     current = ms
                 else:
                     wpm[c], pipe_c[c], ovl_c[c], pack_c[c] = keep
+    # priority boost for the costliest markets (tuning flag bit 1): in a mixed ensemble every
+    # market runs the same steps, so the markets with the most work per step hold the launch's
+    # critical path; kept only if the whole ensemble runs faster by more than the tie margin
+    flags = 0
+    if len(work) > 1:
+        base = dict(ensemble_tuning(), class_cost_ns=cost)
+        t_base = _time_launch(descs, seed, base, S_ens)
+        t_boost = _time_launch(descs, seed, dict(base, flags=BOOST), S_ens)
+        if log:
+            log("ensemble: priority boost %.3f ms (without %.3f)" % (t_boost, t_base))
+        if t_boost < t_base * (1.0 - TIE):
+            flags = BOOST
     if cache:
         allc = {}
         if os.path.exists(cache):
@@ -269,7 +285,7 @@ def tune(descs, seed=0, S_probe=None, min_markets=None, cache=None, arch="gfx950
         os.makedirs(os.path.dirname(os.path.abspath(cache)), exist_ok=True)
         with open(cache, "w") as f:
             json.dump(allc, f, indent=1, sort_keys=True)
-    result = {"waves_per_group": best_g[0],
+    result = {"waves_per_group": best_g[0], "flags": flags,
               "waves_per_market": {int(c): int(w) for c, w in wpm.items()},
               "pipelined": {int(c): 1 for c, p in pipe_c.items() if p},
               "overlap": {int(c): int(k) for c, k in ovl_c.items() if k},

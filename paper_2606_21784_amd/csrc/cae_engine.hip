@@ -66,6 +66,7 @@ struct Item {
     uint32_t share;     // pipe 2: rows of 64 agents the clearing wave generates after clearing
     uint32_t hoff;      // pipe 2: word offset of the two order-bin buffers in a market slice
     uint32_t hwords;    // pipe 2: words per order-bin buffer
+    uint32_t boost;     // 1: its waves issue one priority level above other items' (see base_prio)
 };
 
 constexpr uint32_t kScr = 32;  // scratch words at the end of every market slice
@@ -138,6 +139,22 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Issue priority of a wave that is not clearing.  In a mixed ensemble the markets with the most
+// work per step set the launch's length (every market runs the same number of steps), so their
+// items may be boosted one level above the rest; `hi` selects the upper of the two levels a
+// group alternates between (the clearing wave itself runs at 3).  Levels: boosted 2 / 1, others
+// 1 / 0.  s_setprio takes an immediate, hence the branches.
+__device__ __forceinline__ void base_prio(uint32_t boost, bool hi)
+{
+    if (boost) {
+        if (hi) __builtin_amdgcn_s_setprio(2);
+        else __builtin_amdgcn_s_setprio(1);
+    } else {
+        if (hi) __builtin_amdgcn_s_setprio(1);
+        else __builtin_amdgcn_s_setprio(0);
+    }
 }
 
 struct ClearOut {
@@ -941,7 +958,7 @@ __device__ __forceinline__ void run_market(const EngineArgs &args, const Item &i
             // waves wait for; top issue priority lets it run ahead of other markets' generation
             __builtin_amdgcn_s_setprio(3);
             co = clear_dispatch<TPL_MAX>(bk, d.tpl, lane);
-            __builtin_amdgcn_s_setprio(0);
+            base_prio(item.boost, item.boost != 0u);
             if constexpr (MULTI) {
                 if (lane == 0)
                     *reinterpret_cast<uint4 *>(scr + 4u * (i & 1u)) = make_uint4(co.p, co.v, co.bb, co.ba);
@@ -1170,8 +1187,7 @@ __device__ __forceinline__ void run_market_ovl(const EngineArgs &args, const Ite
             // out of step between workgroups of even and odd index: the SIMD arbiter otherwise
             // favours the oldest waves for the whole persistent launch, and the markets of the
             // youngest workgroups on a CU set the launch's length.
-            if (((i >> kOvlBlockLog2) + blockIdx.x) & 1u) __builtin_amdgcn_s_setprio(1);
-            else __builtin_amdgcn_s_setprio(0);
+            base_prio(item.boost, (((i >> kOvlBlockLog2) + blockIdx.x) & 1u) != 0u);
             const uint32_t r = (w_in - c - 1u) & wpm_mask;  // 0 .. wpm - 2
             gen_rel(d, s + 1u, PhiloxStep(s + 1u, d.id, args.k0, args.k1), own + (r << 6), ostride, d.A, lane,
                     Hn);
@@ -1345,8 +1361,7 @@ __device__ __forceinline__ void run_market_ovl_any(const EngineArgs &args, const
             __builtin_amdgcn_s_setprio(0);
         } else if (active && more) {
             // issue priority alternating by block and workgroup parity, as in run_market_ovl
-            if (((i >> kOvlBlockLog2) + blockIdx.x) & 1u) __builtin_amdgcn_s_setprio(1);
-            else __builtin_amdgcn_s_setprio(0);
+            base_prio(item.boost, (((i >> kOvlBlockLog2) + blockIdx.x) & 1u) != 0u);
             const uint32_t r = (w_in - c - 1u) & wpm_mask;  // 0 .. wpm - 2
             gen_bins(s + 1u, own + (r << 6), ostride, d.A, Hn);
         }
@@ -1947,6 +1962,7 @@ __global__ void __launch_bounds__(1024) cae_engine_kernel(const EngineArgs args)
         __syncthreads();
         if (it >= args.n_items) break;
         const Item item = args.items[it];
+        base_prio(item.boost, item.boost != 0u);
         const uint32_t sub = wave >> item.wpm_log2;
         const uint32_t w_in = wave & ((1u << item.wpm_log2) - 1u);
         const bool active = sub < item.count;
@@ -2416,6 +2432,17 @@ int build_schedule(cae_ensemble *e, const cae_tuning *tn, const uint32_t *ids,
     if (!keep)
         std::stable_sort(done.begin(), done.end(), [](const auto &a, const auto &b) { return a.first > b.first; });
 
+    // Priority boost (tuning flag bit 1): items of lock-step or single-wave markets whose cost
+    // per step is within a quarter of the largest, when some item falls below that (a uniform
+    // ensemble keeps one level for all).
+    const bool boost = (t.flags & 2u) != 0;
+    double cmax = 0.0, cmin = 0.0;
+    for (size_t i = 0; i < done.size(); ++i) {
+        cmax = i ? std::max(cmax, done[i].first) : done[i].first;
+        cmin = i ? std::min(cmin, done[i].first) : done[i].first;
+    }
+    const bool tiers = boost && cmin < 0.75 * cmax;
+
     order.clear();
     items.clear();
     uint32_t lds_max = 0;
@@ -2430,6 +2457,7 @@ int build_schedule(cae_ensemble *e, const cae_tuning *tn, const uint32_t *ids,
         it.share = b.share;
         it.hoff = 2u * 64u * b.tpl;
         it.hwords = b.hw;
+        it.boost = (tiers && (b.pipe == 0u || b.pipe == 2u) && p.first >= 0.75 * cmax) ? 1u : 0u;
         for (uint32_t mm : b.ms) order.push_back(mm);
         items.push_back(it);
         lds_max = std::max(lds_max, it.count * it.stride * 4u);

@@ -589,6 +589,27 @@ def test_overlapped_mixed_with_other_modes():
     _assert_states(st, rst)
 
 
+def test_priority_boost_is_exact():
+    """Tuning flag bit 1 raises the issue priority of the costliest items (here the overlapped
+    markets of 1024 agents among single-wave markets of 16 to 256): the same books and
+    statistics as the oracle, in the same mixed launch with and without it."""
+    from paper_2606_21784_amd import engine
+    parts = []
+    for A in (16, 64, 256, 1024):
+        parts.append(W.uniform(6, 128, A, 8, 10, n_noise=A - A // 4 - A // 8, n_mom=A // 4, h=2))
+    d = np.concatenate(parts)
+    cls = sorted(set(engine.size_class(int(a), int(b)) for a, b in zip(d["L"], d["A"])))
+    big = engine.size_class(128, 1024)
+    base = {"waves_per_group": 4, "waves_per_market": {c: (4 if c == big else 1) for c in cls},
+            "overlap": {big: 3}}
+    rst, rbk = O.run(d, 31, 120)
+    for flags in (0, 2):
+        st, bk, used = _run_gpu(d, 31, [70, 50], tuning=dict(base, flags=flags))
+        assert used["flags"] == flags
+        _assert_books(d, bk, rbk)
+        _assert_states(st, rst)
+
+
 @pytest.mark.parametrize("k", [1, 3, 9])
 def test_overlap_with_mid_price_and_splitmix_markets(k):
     """The overlapped schedule with last-tick and mid-price markets (marketable orders
