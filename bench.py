@@ -225,12 +225,12 @@ def uneven_leg(reps=2):
            "per_size_events_per_s": events / t_split, "speedup_vs_per_size": t_split / t_batched,
            "ceiling_frac": events / t_batched / ensemble_ceiling(d),
            "schedule": {"waves_per_group": sched["waves_per_group"],
-                        "groups_per_cu": sched["groups_per_cu"],
+                        "groups_per_cu": sched["groups_per_cu"], "flags": sched["flags"],
                         "waves_per_market": {str(k): v for k, v in sched["waves_per_market"].items()},
                         "overlap": {str(k): v for k, v in sched["overlap"].items()}},
            "tune_s": tune_s}
-    log("uneven: batched %.1f ms (untuned %.1f), per-size %d launches %.1f ms" %
-        (out["batched_ms"], out["untuned_batched_ms"], len(groups), out["per_size_ms"]))
+    log("uneven: batched %.1f ms (untuned %.1f), per-size %d launches %.1f ms, tuning flags %d" %
+        (out["batched_ms"], out["untuned_batched_ms"], len(groups), out["per_size_ms"], sched["flags"]))
     return out
 
 
@@ -299,7 +299,7 @@ def tuned_time(w, reps=2):
              "waves_per_market": sorted(set(used["waves_per_market"].values())),
              "pipelined": bool(used["pipelined"]),
              "overlap": sorted(set(used["overlap"].values())),
-             "pack": sorted(set(used["pack"].values()))}
+             "pack": sorted(set(used["pack"].values())), "flags": used["flags"]}
     sched["ceiling_frac"] = frac
     return ms, events / (ms * 1e-3), sched, times
 

@@ -153,7 +153,8 @@ def run_sweep(A_values=(16, 64, 256, 1024), alphas=ALPHA_MOM, markets=64, S=1000
               "events_per_s": events / (kernel_ms * 1e-3),
               "schedule": {"waves_per_group": used["waves_per_group"],
                            "waves_per_market": sorted(set(used["waves_per_market"].values())),
-                           "overlap": sorted(set(used["overlap"].values()))}}
+                           "overlap": sorted(set(used["overlap"].values())),
+                           "flags": used["flags"]}}
     return report, timing
 
 
