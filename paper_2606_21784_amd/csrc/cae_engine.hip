@@ -1132,7 +1132,9 @@ __device__ __forceinline__ void run_market_ovl(const EngineArgs &args, const Ite
         uint32_t *Hn = (i & 1u) ? H0 : H1;  // bins of step i + 1
         const bool more = i + 1u < args.S;
         if (active && w_in == c) {
-            __builtin_amdgcn_s_setprio(3);
+            // top issue priority for the whole block (the wave waits at the barrier between its
+            // steps, and the next block's base_prio lowers it again)
+            if ((i & (kOvlBlock - 1u)) == 0u) __builtin_amdgcn_s_setprio(3);
             if (i != 0u && (i & (kOvlBlock - 1u)) == 0u) {  // first step of this wave's block
                 const uint4 h = *reinterpret_cast<const uint4 *>(scr);
                 last = (uint32_t)__builtin_amdgcn_readfirstlane((int)h.x);
@@ -1181,13 +1183,13 @@ __device__ __forceinline__ void run_market_ovl(const EngineArgs &args, const Ite
                 n_spread += b_nspread;
                 b_trade = b_vol = b_px = b_spread = b_nspread = 0u;
             }
-            __builtin_amdgcn_s_setprio(0);
         } else if (active && more) {
             // Generating waves alternate between issue priorities 0 and 1 every block of steps,
             // out of step between workgroups of even and odd index: the SIMD arbiter otherwise
             // favours the oldest waves for the whole persistent launch, and the markets of the
-            // youngest workgroups on a CU set the launch's length.
-            base_prio(item.boost, (((i >> kOvlBlockLog2) + blockIdx.x) & 1u) != 0u);
+            // youngest workgroups on a CU set the launch's length.  Set once per block.
+            if ((i & (kOvlBlock - 1u)) == 0u)
+                base_prio(item.boost, (((i >> kOvlBlockLog2) + blockIdx.x) & 1u) != 0u);
             const uint32_t r = (w_in - c - 1u) & wpm_mask;  // 0 .. wpm - 2
             gen_rel(d, s + 1u, PhiloxStep(s + 1u, d.id, args.k0, args.k1), own + (r << 6), ostride, d.A, lane,
                     Hn);
