@@ -72,6 +72,9 @@ def _time_launch(descs, seed, tuning, S, reps=3):
 # Probe launches are sized to about this many agent events (roughly a millisecond), so that
 # launch overhead and timer resolution stay below the differences between candidates.
 PROBE_EVENTS = 5e8
+# The whole-ensemble stages (workgroup size, runner-up schedules, priority boost) decide between
+# schedules a few percent apart, so their probes run four times longer.
+ENSEMBLE_PROBE_EVENTS = 2e9
 
 
 def probe_steps(descs, S_min=20, S_max=1000, events=PROBE_EVENTS):
@@ -217,18 +220,23 @@ def tune(descs, seed=0, S_probe=None, min_markets=None, cache=None, arch="gfx950
                 return x[0], x[1], x[3], x[5]
         return min(wpm[c], G), pipe_c[c] and G >= 2, ovl_c.get(c, 0), pack_c[c]
 
+    # two rounds over the sizes, keeping each size's best, so that a drift of the clocks during
+    # the stage does not favour the sizes timed last
     best_g = None
-    for G in GROUP_CANDIDATES:
-        sel = {c: fitting(c, G) for c in wpm}
-        tn = {"waves_per_group": G, "waves_per_market": {int(c): v[0] for c, v in sel.items()},
-              "pipelined": {int(c): 1 for c, v in sel.items() if v[1]},
-              "overlap": {int(c): v[2] for c, v in sel.items() if v[2]},
-              "pack": {int(c): v[3] for c, v in sel.items() if v[3]}}
-        ms = _time_launch(descs, seed, tn, S_probe or probe_steps(descs))
-        if log:
-            log("waves_per_group %2d: %.3f ms" % (G, ms))
-        if best_g is None or ms < best_g[1]:
-            best_g = (G, ms, sel)
+    g_ms = {}
+    for _ in range(2):
+        for G in GROUP_CANDIDATES:
+            sel = {c: fitting(c, G) for c in wpm}
+            tn = {"waves_per_group": G, "waves_per_market": {int(c): v[0] for c, v in sel.items()},
+                  "pipelined": {int(c): 1 for c, v in sel.items() if v[1]},
+                  "overlap": {int(c): v[2] for c, v in sel.items() if v[2]},
+                  "pack": {int(c): v[3] for c, v in sel.items() if v[3]}}
+            ms = _time_launch(descs, seed, tn, S_probe or probe_steps(descs, events=ENSEMBLE_PROBE_EVENTS))
+            g_ms[G] = min(ms, g_ms.get(G, ms))
+            if log:
+                log("waves_per_group %2d: %.3f ms" % (G, ms))
+            if best_g is None or g_ms[G] < best_g[1]:
+                best_g = (G, g_ms[G], sel)
     for c, v in best_g[2].items():
         wpm[c], pipe_c[c], ovl_c[c], pack_c[c] = v
     # whole-ensemble stage: a class's own probe fills the GPU with that class alone, while in a
@@ -237,7 +245,7 @@ def tune(descs, seed=0, S_probe=None, min_markets=None, cache=None, arch="gfx950
     # schedule of the class is tried in the whole ensemble and kept if it is faster by more than
     # the tie margin.
     G = best_g[0]
-    S_ens = S_probe or probe_steps(descs)
+    S_ens = S_probe or probe_steps(descs, events=ENSEMBLE_PROBE_EVENTS)
 
     def ensemble_tuning():
         return {"waves_per_group": G, "waves_per_market": {int(c): w for c, w in wpm.items()},
