@@ -608,6 +608,15 @@ def test_priority_boost_is_exact():
         assert used["flags"] == flags
         _assert_books(d, bk, rbk)
         _assert_states(st, rst)
+    # the same mix with half the markets on the mid-price model (the instantiation that may meet
+    # it runs its own overlapped loop)
+    d2 = d.copy()
+    d2["flags"][::2] = O.model_flags(O.MODEL_MID, 3277)
+    rst2, rbk2 = O.run(d2, 32, 120)
+    for flags in (0, 2):
+        st, bk, used = _run_gpu(d2, 32, [64, 56], tuning=dict(base, flags=flags))
+        _assert_books(d2, bk, rbk2)
+        _assert_states(st, rst2)
 
 
 @pytest.mark.parametrize("k", [1, 3, 9])
