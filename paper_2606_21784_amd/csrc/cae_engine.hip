@@ -1634,6 +1634,13 @@ __device__ __forceinline__ uint32_t seg_crossing_lane(bool pred, uint32_t base)
     return base + (uint32_t)__builtin_ctz(seg_bits<SEGLOG>(ballot(pred), base) | (1u << (kSeg - 1u)));
 }
 
+// Packed books hold two (bid, ask) pairs of padding after every 32 ticks: a segment's lanes read
+// their ticks as runs of TPL pairs, and without the padding the lanes of one 16-lane LDS pass
+// whose runs start 256 bytes apart would share banks.  Pair index of tick q, and the LDS word of
+// book word w = 2 q + side.
+__device__ __forceinline__ uint32_t pad_pair(uint32_t q) { return q + 2u * (q >> 5); }
+__device__ __forceinline__ uint32_t pad_word(uint32_t w) { return w + ((w >> 6) << 2); }
+
 // One clearing pass over the book of each lane segment (bk: this lane's book, pairs for ticks
 // [0, SEG TPL), zero beyond L; ll: the lane's index in its segment; wr: the segment holds a
 // market, so its residual book is written back).  Segment-uniform result.
@@ -1642,7 +1649,7 @@ __device__ __forceinline__ ClearOut clear_seg(uint32_t *__restrict__ bk, uint32_
 {
     const uint32_t q0 = ll * TPL;
     uint32_t b[TPL], k[TPL];
-    load_pairs<TPL>(bk, q0, b, k);
+    load_pairs<TPL>(bk, pad_pair(q0), b, k);
     uint32_t sb = 0, sa = 0;
 #pragma unroll
     for (int j = 0; j < TPL; ++j) {
@@ -1682,7 +1689,7 @@ __device__ __forceinline__ ClearOut clear_seg(uint32_t *__restrict__ bk, uint32_
         ud = ud1;
         us = us1;
     }
-    if (wr) store_pairs<TPL>(bk, q0, b, k);
+    if (wr) store_pairs<TPL>(bk, pad_pair(q0), b, k);
     uint32_t hb = kNone, la = kNone;
 #pragma unroll
     for (int j = 0; j < TPL; ++j)
@@ -1740,7 +1747,7 @@ __device__ __forceinline__ ClearOut clear_row(uint32_t *__restrict__ bk, uint32_
 {
     const uint32_t q0 = ll * TPL;
     uint32_t b[TPL], k[TPL];
-    load_pairs<TPL>(bk, q0, b, k);
+    load_pairs<TPL>(bk, pad_pair(q0), b, k);
     uint32_t sb = 0, sa = 0;
 #pragma unroll
     for (int j = 0; j < TPL; ++j) {
@@ -1788,7 +1795,7 @@ __device__ __forceinline__ ClearOut clear_row(uint32_t *__restrict__ bk, uint32_
         ud = ud1;
         us = us1;
     }
-    if (wr) store_pairs<TPL>(bk, q0, b, k);
+    if (wr) store_pairs<TPL>(bk, pad_pair(q0), b, k);
     // the three counts in one row sum, in 10-bit fields (a row has at most 16 TPL = 128 ticks)
     const uint32_t tot = row_sum(cp | (cb << 10) | (cs << 20));
     out.p = tot & 1023u;
@@ -1851,7 +1858,7 @@ __device__ __forceinline__ void run_packed_seg(const EngineArgs &args, const Ite
                 v.x = gb[q];
                 v.y = gb[d.L + q];
             }
-            reinterpret_cast<uint2 *>(bk)[q] = v;
+            reinterpret_cast<uint2 *>(bk)[pad_pair(q)] = v;
         }
     }
     wave_sync();
@@ -1876,7 +1883,7 @@ __device__ __forceinline__ void run_packed_seg(const EngineArgs &args, const Ite
                     uint32_t w0, w1, w2, w3 = 0;
                     gen.words4(a, w0, w1, w2, w3);
                     const uint32_t w = a >= o.n_noise ? other_word<false>(o, a, w0, w3) : noise_word(o, w0, w1);
-                    atomicAdd(&bk[w], order_qty(o, w2));
+                    atomicAdd(&bk[pad_word(w)], order_qty(o, w2));
                 }
             }
         }
@@ -1918,7 +1925,7 @@ __device__ __forceinline__ void run_packed_seg(const EngineArgs &args, const Ite
     if (active) {
         uint32_t *gb = args.book + d.book_off;
         for (uint32_t q = ll; q < d.L; q += kSeg) {
-            const uint2 v = reinterpret_cast<const uint2 *>(bk)[q];
+            const uint2 v = reinterpret_cast<const uint2 *>(bk)[pad_pair(q)];
             gb[q] = v.x;
             gb[d.L + q] = v.y;
         }
@@ -2406,7 +2413,7 @@ int build_schedule(cae_ensemble *e, const cae_tuning *tn, const uint32_t *ids,
             hw = 1u;
             while (seg * hw < e->desc[m].L) hw <<= 1;
             tp = 0u;
-            stride = 2u * seg * hw + kScr;
+            stride = 2u * seg * hw + 4u * ((seg * hw + 31u) / 32u) + kScr;  // padded (pad_pair)
             cap = G * packp[m];
         }
         cap = std::max(1u, std::min(cap, lds_budget / (stride * 4u)));
@@ -2454,7 +2461,10 @@ int build_schedule(cae_ensemble *e, const cae_tuning *tn, const uint32_t *ids,
         it.first = (uint32_t)order.size();
         it.count = (uint32_t)b.ms.size();
         it.wpm_log2 = (uint32_t)__builtin_ctz(b.wpm);
-        it.stride = b.pipe == 3u ? 2u * (64u / b.share) * b.hw + kScr : 2u * 64u * b.tpl + 2u * b.hw + kScr;
+        // packed books: 2 words per tick plus 4 words of padding per 32 ticks (pad_pair)
+        const uint32_t pticks = b.pipe == 3u ? (64u / b.share) * b.hw : 0u;
+        it.stride = b.pipe == 3u ? 2u * pticks + 4u * ((pticks + 31u) / 32u) + kScr
+                                 : 2u * 64u * b.tpl + 2u * b.hw + kScr;
         it.pipe = b.pipe;
         it.share = b.share;
         it.hoff = 2u * 64u * b.tpl;
