@@ -1642,14 +1642,16 @@ __device__ __forceinline__ uint32_t pad_pair(uint32_t q) { return q + 2u * (q >>
 __device__ __forceinline__ uint32_t pad_word(uint32_t w) { return w + ((w >> 6) << 2); }
 
 // One clearing pass over the book of each lane segment (bk: this lane's book, pairs for ticks
-// [0, SEG TPL), zero beyond L; ll: the lane's index in its segment; wr: the segment holds a
-// market, so its residual book is written back).  Segment-uniform result.
-template <int TPL, int SEGLOG>
-__device__ __forceinline__ ClearOut clear_seg(uint32_t *__restrict__ bk, uint32_t ll, uint32_t base, bool wr)
+// [0, SEG TPL), zero beyond L, its residual written back; ll: the lane's index in its segment;
+// mid: independent work issued after the book loads, which the pass's own dependency chain leaves
+// room for).  Segment-uniform result.
+template <int TPL, int SEGLOG, class F>
+__device__ __forceinline__ ClearOut clear_seg(uint32_t *__restrict__ bk, uint32_t ll, uint32_t base, F &&mid)
 {
     const uint32_t q0 = ll * TPL;
     uint32_t b[TPL], k[TPL];
     load_pairs<TPL>(bk, pad_pair(q0), b, k);
+    mid();
     uint32_t sb = 0, sa = 0;
 #pragma unroll
     for (int j = 0; j < TPL; ++j) {
@@ -1689,7 +1691,7 @@ __device__ __forceinline__ ClearOut clear_seg(uint32_t *__restrict__ bk, uint32_
         ud = ud1;
         us = us1;
     }
-    if (wr) store_pairs<TPL>(bk, pad_pair(q0), b, k);
+    store_pairs<TPL>(bk, pad_pair(q0), b, k);
     uint32_t hb = kNone, la = kNone;
 #pragma unroll
     for (int j = 0; j < TPL; ++j)
@@ -1737,17 +1739,18 @@ __device__ __forceinline__ uint32_t row_max(uint32_t x)
 }
 
 // One clearing pass over the book of each 16-lane segment (four books per wave), TPL ticks per
-// lane (ll: the lane's index in its segment; wr: the segment holds a market).  By the definitions:
+// lane (ll: the lane's index in its segment; mid: as in clear_seg).  By the definitions:
 // V* = max over ticks of min(D, S) (a row maximum of the lanes' maxima); since S rises with the
 // tick, the lowest tick with V = V* is the number of ticks with S < V* (a row sum); the best
 // quotes after the fill are counts of ticks too, summed with it.  D and S of each tick are re-formed by
 // running sums in every pass, so only the book words stay live.  Segment-uniform result.
-template <int TPL>
-__device__ __forceinline__ ClearOut clear_row(uint32_t *__restrict__ bk, uint32_t ll, bool wr)
+template <int TPL, class F>
+__device__ __forceinline__ ClearOut clear_row(uint32_t *__restrict__ bk, uint32_t ll, F &&mid)
 {
     const uint32_t q0 = ll * TPL;
     uint32_t b[TPL], k[TPL];
     load_pairs<TPL>(bk, pad_pair(q0), b, k);
+    mid();
     uint32_t sb = 0, sa = 0;
 #pragma unroll
     for (int j = 0; j < TPL; ++j) {
@@ -1768,19 +1771,11 @@ __device__ __forceinline__ ClearOut clear_row(uint32_t *__restrict__ bk, uint32_
     ClearOut out;
     out.v = row_max(mv);
     const uint32_t vs = out.v;
-    uint32_t cp = 0;  // ticks with S < V*: the clearing tick is their number
-    {
-        uint32_t t = Sb;
-#pragma unroll
-        for (int j = 0; j < TPL; ++j) {
-            t += k[j];
-            cp += nonzero(unmatched(vs, t));
-        }
-    }
-    // the fill, counting the ticks with D > V* (the best bid after the fill is the highest such
-    // tick: the unmatched demand max(D - V*, 0) falls with the tick and the residual bids are
-    // its drops) and with S > V* (the best ask is the lowest such tick)
-    uint32_t ud = unmatched(D0, vs), us = unmatched(Sb, vs), cb = 0, cs = 0;
+    // the fill, counting the ticks with S < V* (the clearing tick is their number), with D > V*
+    // (the best bid after the fill is the highest such tick: the unmatched demand max(D - V*, 0)
+    // falls with the tick and the residual bids are its drops) and with S > V* (the best ask is
+    // the lowest such tick)
+    uint32_t ud = unmatched(D0, vs), us = unmatched(Sb, vs), cp = 0, cb = 0, cs = 0;
     d = D0;
     sq = Sb;
 #pragma unroll
@@ -1788,6 +1783,7 @@ __device__ __forceinline__ ClearOut clear_row(uint32_t *__restrict__ bk, uint32_
         d -= b[j];
         sq += k[j];
         const uint32_t ud1 = unmatched(d, vs), us1 = unmatched(sq, vs);
+        cp += nonzero(unmatched(vs, sq));
         cb += nonzero(ud);
         cs += nonzero(us1);
         b[j] = ud - ud1;
@@ -1795,7 +1791,7 @@ __device__ __forceinline__ ClearOut clear_row(uint32_t *__restrict__ bk, uint32_
         ud = ud1;
         us = us1;
     }
-    if (wr) store_pairs<TPL>(bk, pad_pair(q0), b, k);
+    store_pairs<TPL>(bk, pad_pair(q0), b, k);
     // the three counts in one row sum, in 10-bit fields (a row has at most 16 TPL = 128 ticks)
     const uint32_t tot = row_sum(cp | (cb << 10) | (cs << 20));
     out.p = tot & 1023u;
@@ -1805,20 +1801,20 @@ __device__ __forceinline__ ClearOut clear_row(uint32_t *__restrict__ bk, uint32_
     return out;
 }
 
-template <int SEGLOG>
+template <int SEGLOG, class F>
 __device__ __forceinline__ ClearOut clear_seg_dispatch(uint32_t *bk, uint32_t tpl, uint32_t ll, uint32_t base,
-                                                       bool wr)
+                                                       F &&mid)
 {
     if constexpr (SEGLOG == 4) {  // 16-lane segments (DPP rows) hold books of up to 128 ticks
         (void)base;
-        if (tpl >= 8u) return clear_row<8>(bk, ll, wr);
-        if (tpl >= 4u) return clear_row<4>(bk, ll, wr);
-        if (tpl == 2u) return clear_row<2>(bk, ll, wr);
-        return clear_row<1>(bk, ll, wr);
+        if (tpl >= 8u) return clear_row<8>(bk, ll, mid);
+        if (tpl >= 4u) return clear_row<4>(bk, ll, mid);
+        if (tpl == 2u) return clear_row<2>(bk, ll, mid);
+        return clear_row<1>(bk, ll, mid);
     }
-    if (tpl >= 4u) return clear_seg<4, SEGLOG>(bk, ll, base, wr);
-    if (tpl == 2u) return clear_seg<2, SEGLOG>(bk, ll, base, wr);
-    return clear_seg<1, SEGLOG>(bk, ll, base, wr);
+    if (tpl >= 4u) return clear_seg<4, SEGLOG>(bk, ll, base, mid);
+    if (tpl == 2u) return clear_seg<2, SEGLOG>(bk, ll, base, mid);
+    return clear_seg<1, SEGLOG>(bk, ll, base, mid);
 }
 
 // All S steps of the packed markets of one wave (wave `wave` of the item takes markets
@@ -1829,11 +1825,14 @@ __device__ __forceinline__ void run_packed_seg(const EngineArgs &args, const Ite
 {
     constexpr uint32_t kSeg = 1u << SEGLOG;
     constexpr uint32_t kP = 64u / kSeg;
+    if (wave * kP >= item.count) return;  // a wave beyond the item's markets has no LDS slots
     const uint32_t seg = lane >> SEGLOG, ll = lane & (kSeg - 1u), base = seg << SEGLOG;
     const uint32_t slot = wave * kP + seg;
     const bool active = slot < item.count;
     const uint32_t tpl = item.hwords;
-    uint32_t *bk = lds + (active ? slot : 0u) * item.stride;
+    // every slot of the item's waves has its LDS (the item's share is whole waves), so a segment
+    // without a market clears an empty book of its own, and the clearing has no masked store
+    uint32_t *bk = lds + slot * item.stride;
     // the integer statistics live in the slot's scratch words (64-bit LDS adds by the segment's
     // first lane), which keeps registers for the per-lane generator and clearing
     uint64_t *acc = reinterpret_cast<uint64_t *>(bk + item.stride - kScr);
@@ -1851,7 +1850,9 @@ __device__ __forceinline__ void run_packed_seg(const EngineArgs &args, const Ite
         sum_r = st->sum_r;
         sum_r2 = st->sum_r2;
         if (ll < 5u) acc[ll] = (&st->n_trade)[ll];  // n_trade, sum_vol, sum_px, sum_spread, n_spread
-        const uint32_t *gb = args.book + d.book_off;
+    }
+    {
+        const uint32_t *gb = args.book + d.book_off;  // d.L = 0 without a market
         for (uint32_t q = ll; q < kSeg * tpl; q += kSeg) {
             uint2 v = make_uint2(0u, 0u);
             if (q < d.L) {
@@ -1867,30 +1868,43 @@ __device__ __forceinline__ void run_packed_seg(const EngineArgs &args, const Ite
     // each step's log return is added at the end of the next step, whose start issues the table
     // load (long back by then); ln_prev = ln(L + price) before the step whose return is pending
     double ln_prev = active ? lnT[last] : 0.0;
+    // the generator words of agent ll (the first row) for the coming step: they do not depend on
+    // the book, so each step's clearing pass computes the next step's alongside its own chain
+    // (every lane computes them, unmasked, so that they share the clearing's basic block; only
+    // lanes with an agent use them)
+    uint32_t pw0, pw1, pw2, pw3;
+    const bool row0 = ll < A;
+    PhiloxStep(s0, d.id, args.k0, args.k1).words4(ll, pw0, pw1, pw2, pw3);
     for (uint32_t i = 0; i < args.S; ++i) {
         const uint32_t s = s0 + i;
         const double ln_cur = (active && i >= 1u) ? lnT[last] : 0.0;
         {
             const OrderCtx o = order_ctx<false>(d, s, Refs{last, prev, 2u * last, 0u});
-            const PhiloxStep gen(s, d.id, args.k0, args.k1);
-            // rows of SEG agents until every segment's market is done (the markets of a wave
-            // may have different populations)
-            for (uint32_t b0 = 0;; b0 += kSeg) {
-                const uint32_t a = b0 + ll;
-                const bool on = a < A;
-                if (!ballot(on)) break;
-                if (on) {
-                    uint32_t w0, w1, w2, w3 = 0;
-                    gen.words4(a, w0, w1, w2, w3);
-                    const uint32_t w = a >= o.n_noise ? other_word<false>(o, a, w0, w3) : noise_word(o, w0, w1);
-                    atomicAdd(&bk[pad_word(w)], order_qty(o, w2));
+            if (row0) {
+                const uint32_t w = ll >= o.n_noise ? other_word<false>(o, ll, pw0, pw3) : noise_word(o, pw0, pw1);
+                atomicAdd(&bk[pad_word(w)], order_qty(o, pw2));
+            }
+            // further rows of SEG agents until every segment's market is done (the markets of a
+            // wave may have different populations)
+            if (ballot(kSeg < A)) {
+                const PhiloxStep gen(s, d.id, args.k0, args.k1);
+                for (uint32_t b0 = kSeg;; b0 += kSeg) {
+                    const uint32_t a = b0 + ll;
+                    const bool on = a < A;
+                    if (!ballot(on)) break;
+                    if (on) {
+                        uint32_t w0, w1, w2, w3 = 0;
+                        gen.words4(a, w0, w1, w2, w3);
+                        const uint32_t w = a >= o.n_noise ? other_word<false>(o, a, w0, w3) : noise_word(o, w0, w1);
+                        atomicAdd(&bk[pad_word(w)], order_qty(o, w2));
+                    }
                 }
             }
         }
         wave_sync();
-        // a segment without a market reads slot 0's book (its lanes point there) but writes
-        // nothing
-        const ClearOut co = clear_seg_dispatch<SEGLOG>(bk, tpl, ll, base, active);
+        const ClearOut co = clear_seg_dispatch<SEGLOG>(bk, tpl, ll, base, [&] {
+            PhiloxStep(s + 1u, d.id, args.k0, args.k1).words4(ll, pw0, pw1, pw2, pw3);
+        });
         if (active) {
             prev = last;
             if (co.v != 0) last = co.p;
@@ -2417,6 +2431,7 @@ int build_schedule(cae_ensemble *e, const cae_tuning *tn, const uint32_t *ids,
             cap = G * packp[m];
         }
         cap = std::max(1u, std::min(cap, lds_budget / (stride * 4u)));
+        if (packp[m] && cap > packp[m]) cap -= cap % packp[m];  // whole waves (the LDS holds them)
         Bin *b = nullptr;
         for (auto &x : open)
             if (x.wpm == w && x.tpl == tp && x.pipe == pp && x.share == share && x.hw == hw) b = &x;
@@ -2472,7 +2487,9 @@ int build_schedule(cae_ensemble *e, const cae_tuning *tn, const uint32_t *ids,
         it.boost = (tiers && (b.pipe == 0u || b.pipe == 2u) && p.first >= 0.75 * cmax) ? 1u : 0u;
         for (uint32_t mm : b.ms) order.push_back(mm);
         items.push_back(it);
-        lds_max = std::max(lds_max, it.count * it.stride * 4u);
+        // packed items hold LDS for every slot of their waves, markets or not
+        const uint32_t slots = b.pipe == 3u ? (it.count + b.share - 1u) / b.share * b.share : it.count;
+        lds_max = std::max(lds_max, slots * it.stride * 4u);
     }
 
     // device descriptors
