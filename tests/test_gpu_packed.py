@@ -92,6 +92,16 @@ def test_packed_four_books_of_128_ticks(G):
     assert set(used["pack"].values()) == {4}
 
 
+@pytest.mark.parametrize("budget", [6500, 2000])
+def test_packed_lds_budget_not_whole_waves(budget):
+    """An LDS budget that fits 5 packed 128-tick books (4 per wave) keeps items of whole waves
+    (4 books), and one that fits only one book still runs: every slot of an item's waves has its
+    LDS, the empty segments of a wave included."""
+    d = W.uniform(13, 128, 16, 8, 10)
+    tn = dict(_pack_all(4, 8), max_lds_bytes=budget)
+    _check(d, 31, [25, 4], tn)
+
+
 def test_packed_populations_differ_within_a_wave():
     """Markets of one size class (A below 128) with different populations and grids share waves."""
     rng = np.random.default_rng(3)
