@@ -371,6 +371,10 @@ typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 constexpr uint32_t kTrainRows = 16;
 constexpr uint32_t kRowWaves = 16;   // waves of an mlp_train_rows workgroup: one 16-column tile each at H = 256
 constexpr uint32_t kParamSplit = 4;  // waves that reduce one weight-gradient tile, each a quarter of the batch
+// reduction steps whose global operand loads are issued together before their matrix-core chain
+// (the chain's order, and so every rounding, is the step-by-step one)
+constexpr uint32_t kLoadAhead = 8;
+constexpr uint32_t kGatherAhead = 4;  // the same for the 2-byte W3 gathers (one register each)
 constexpr uint32_t kTrainMaxH = 256;
 constexpr uint32_t kTrainMaxIn = 32;
 constexpr uint32_t kTrainPad = 8;  // bf16 elements of padding per LDS row
@@ -472,8 +476,19 @@ __global__ void __launch_bounds__(kRowWaves * 64) mlp_train_rows(const TrainArgs
     for (uint32_t j = wave; j < ct; j += kRowWaves) {
         const uint32_t n = 16u * j + r;
         v4f acc = {0.f, 0.f, 0.f, 0.f};
-        for (uint32_t k0 = 0; k0 < H; k0 += 32u)
-            acc = mfma32(ld8(h1s + r * ldh + k0 + 8u * g), ld8(a.W2T + (size_t)n * H + k0 + 8u * g), acc);
+        for (uint32_t k0 = 0; k0 < H; k0 += 32u * kLoadAhead) {
+            v8bf wf[kLoadAhead];  // the chunk's weight fragments, in flight together
+#pragma unroll
+            for (uint32_t u = 0; u < kLoadAhead; ++u) {
+                const uint32_t k = k0 + 32u * u;
+                if (k < H) wf[u] = ld8(a.W2T + (size_t)n * H + k + 8u * g);
+            }
+#pragma unroll
+            for (uint32_t u = 0; u < kLoadAhead; ++u) {
+                const uint32_t k = k0 + 32u * u;
+                if (k < H) acc = mfma32(ld8(h1s + r * ldh + k + 8u * g), wf[u], acc);
+            }
+        }
         uint16_t hb[4];
 #pragma unroll
         for (uint32_t t = 0; t < 4u; ++t) {
@@ -489,12 +504,29 @@ __global__ void __launch_bounds__(kRowWaves * 64) mlp_train_rows(const TrainArgs
     // layer 3, loss and its gradient (one wave): y = h2 W3 + b3; dy = dloss/dy, zero past the batch
     if (wave == 0) {
         v4f acc = {0.f, 0.f, 0.f, 0.f};
-        for (uint32_t k0 = 0; k0 < H; k0 += 32u) {
-            uint16_t e[8];
+        // W3 column r (a lane past d_out reads column 0 and zeroes it: no branch around the
+        // loads, so a chunk's gathers are in flight together)
+        const bool rin = r < a.dout;
+        const uint32_t rc = rin ? r : 0u;
+        for (uint32_t k0 = 0; k0 < H; k0 += 32u * kGatherAhead) {
+            uint16_t e[kGatherAhead][8];
 #pragma unroll
-            for (uint32_t t = 0; t < 8u; ++t)
-                e[t] = r < a.dout ? a.W3[(size_t)(k0 + 8u * g + t) * a.dout + r] : (uint16_t)0;
-            acc = mfma32(ld8(h2s + r * ldh + k0 + 8u * g), pack8(e), acc);
+            for (uint32_t u = 0; u < kGatherAhead; ++u) {
+                const uint32_t k = k0 + 32u * u;
+                if (k < H) {
+#pragma unroll
+                    for (uint32_t t = 0; t < 8u; ++t) e[u][t] = a.W3[(size_t)(k + 8u * g + t) * a.dout + rc];
+                }
+            }
+#pragma unroll
+            for (uint32_t u = 0; u < kGatherAhead; ++u) {
+                const uint32_t k = k0 + 32u * u;
+                if (k < H) {
+#pragma unroll
+                    for (uint32_t t = 0; t < 8u; ++t) e[u][t] = rin ? e[u][t] : (uint16_t)0;
+                    acc = mfma32(ld8(h2s + r * ldh + k + 8u * g), pack8(e[u]), acc);
+                }
+            }
         }
         float ls = 0.f;
         uint16_t db[4];
@@ -549,8 +581,19 @@ __global__ void __launch_bounds__(kRowWaves * 64) mlp_train_rows(const TrainArgs
     for (uint32_t j = wave; j < ct; j += kRowWaves) {
         const uint32_t n = 16u * j + r;
         v4f acc = {0.f, 0.f, 0.f, 0.f};
-        for (uint32_t k0 = 0; k0 < H; k0 += 32u)
-            acc = mfma32(ld8(dzs + r * ldh + k0 + 8u * g), ld8(a.W2 + (size_t)n * H + k0 + 8u * g), acc);
+        for (uint32_t k0 = 0; k0 < H; k0 += 32u * kLoadAhead) {
+            v8bf wf[kLoadAhead];
+#pragma unroll
+            for (uint32_t u = 0; u < kLoadAhead; ++u) {
+                const uint32_t k = k0 + 32u * u;
+                if (k < H) wf[u] = ld8(a.W2 + (size_t)n * H + k + 8u * g);
+            }
+#pragma unroll
+            for (uint32_t u = 0; u < kLoadAhead; ++u) {
+                const uint32_t k = k0 + 32u * u;
+                if (k < H) acc = mfma32(ld8(dzs + r * ldh + k + 8u * g), wf[u], acc);
+            }
+        }
         uint16_t zb[4];
 #pragma unroll
         for (uint32_t t = 0; t < 4u; ++t) zb[t] = f2bf(acc[t] * dsilu(z1s[(4u * g + t) * H + n]));
@@ -612,10 +655,19 @@ __global__ void __launch_bounds__(kParamSplit * 64) mlp_train_params(const Train
     // then added in wave order (a fixed order: deterministic)
     __shared__ v4f part[kParamSplit][64];
     v4f acc = {0.f, 0.f, 0.f, 0.f};
-    for (uint32_t b0 = 32u * wave; b0 < a.Bp; b0 += 32u * kParamSplit) {
-        const v8bf av = arow ? ld8(ap + b0) : (i == M ? ones : zero);
-        const v8bf bv = brow ? ld8(bp + b0) : zero;
-        acc = mfma32(av, bv, acc);
+    for (uint32_t c0 = 32u * wave; c0 < a.Bp; c0 += 32u * kParamSplit * kLoadAhead) {
+        v8bf av[kLoadAhead], bv[kLoadAhead];  // the chunk's fragments, in flight together
+#pragma unroll
+        for (uint32_t u = 0; u < kLoadAhead; ++u) {
+            const uint32_t b0 = c0 + 32u * kParamSplit * u;
+            if (b0 < a.Bp) {
+                av[u] = arow ? ld8(ap + b0) : (i == M ? ones : zero);
+                bv[u] = brow ? ld8(bp + b0) : zero;
+            }
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < kLoadAhead; ++u)
+            if (c0 + 32u * kParamSplit * u < a.Bp) acc = mfma32(av[u], bv[u], acc);
     }
     part[wave][lane] = acc;
     __syncthreads();
