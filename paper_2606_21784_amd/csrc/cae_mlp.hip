@@ -374,7 +374,6 @@ constexpr uint32_t kParamSplit = 4;  // waves that reduce one weight-gradient ti
 // reduction steps whose global operand loads are issued together before their matrix-core chain
 // (the chain's order, and so every rounding, is the step-by-step one)
 constexpr uint32_t kLoadAhead = 8;
-constexpr uint32_t kGatherAhead = 4;  // the same for the 2-byte W3 gathers (one register each)
 constexpr uint32_t kTrainMaxH = 256;
 constexpr uint32_t kTrainMaxIn = 32;
 constexpr uint32_t kTrainPad = 8;  // bf16 elements of padding per LDS row
@@ -422,6 +421,13 @@ struct TrainArgs {
     uint32_t tiles1, tiles2, tiles3;  // gradient tiles of W1|b1, W2|b2, W3|b3
 };
 
+// Every operand that does not depend on the rows (the wave's weight fragments and biases, and
+// wave 0's targets) is loaded before the phase that precedes its use, so that each phase's
+// memory latency overlaps the one before instead of following a barrier; W3, which layer 3
+// gathers column by column, is copied to LDS at the start.  At H <= 256 a wave owns
+// one 16-column tile and a reduction over H is at most kLoadAhead matrix-core steps.
+static_assert(kTrainMaxH <= 16u * kRowWaves && kTrainMaxH <= 32u * kLoadAhead, "one tile per wave, one load chunk");
+
 __global__ void __launch_bounds__(kRowWaves * 64) mlp_train_rows(const TrainArgs a)
 {
     extern __shared__ __align__(16) unsigned char tlds[];
@@ -436,6 +442,40 @@ __global__ void __launch_bounds__(kRowWaves * 64) mlp_train_rows(const TrainArgs
     uint16_t *dzs = h2s + kTrainRows * ldh;
     float *z1s = reinterpret_cast<float *>(dzs + kTrainRows * ldh);  // [16][H]
     float *z2s = z1s + kTrainRows * H;
+    uint16_t *w3s = reinterpret_cast<uint16_t *>(z2s + kTrainRows * H);  // W3 [H][d_out]
+    const bool tile = wave < ct;  // the wave's output columns n = 16 wave + (lane % 16)
+    const uint32_t n = 16u * wave + r;
+    // W3 (at most 256 x 16) for layer 3 and the dz2 step, copied to LDS by the whole workgroup
+    for (uint32_t i = threadIdx.x; i < H * a.dout; i += kRowWaves * 64u) w3s[i] = a.W3[i];
+    // the wave's operands of layer 1 (W1 column n) and layer 2 (W2T row n), and both biases
+    uint16_t e1[8];
+    v8bf w2t[kLoadAhead];
+    float b1n = 0.f, b2n = 0.f;
+    if (tile) {
+#pragma unroll
+        for (uint32_t t = 0; t < 8u; ++t) {
+            const uint32_t k = 8u * g + t;
+            e1[t] = k < a.din ? a.W1[(size_t)k * H + n] : (uint16_t)0;
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < kLoadAhead; ++u)
+            if (32u * u < H) w2t[u] = ld8(a.W2T + (size_t)n * H + 32u * u + 8u * g);
+        b1n = a.p[a.l.b1 + n];
+        b2n = a.p[a.l.b2 + n];
+    }
+    // wave 0's layer-3 operands: b3 and the rows' targets (zero past the batch or d_out)
+    float b3r = 0.f, tv[4] = {0.f, 0.f, 0.f, 0.f};
+    if (wave == 0) {
+        if (r < a.dout) b3r = a.p[a.l.b3 + r];
+#pragma unroll
+        for (uint32_t t = 0; t < 4u; ++t) {
+            const uint32_t row = row0 + 4u * g + t;
+            if (row < a.B && r < a.dout) {
+                const uint32_t src = a.idx ? a.idx[row] : row;
+                tv[t] = a.t[(size_t)src * a.dout + r];
+            }
+        }
+    }
     // inputs of the rows (zero past the batch), their transposed copy, and a zeroed dy tile
     for (uint32_t i = threadIdx.x; i < kTrainRows * 32u; i += kRowWaves * 64u) {
         const uint32_t rr = i / 32u, c = i % 32u, row = row0 + rr;
@@ -450,21 +490,14 @@ __global__ void __launch_bounds__(kRowWaves * 64) mlp_train_rows(const TrainArgs
     }
     __syncthreads();
     // layer 1: z1 = x W1 + b1, h1 = silu(z1)  (one reduction step: d_in <= 32)
-    for (uint32_t j = wave; j < ct; j += kRowWaves) {
-        const uint32_t n = 16u * j + r;
-        uint16_t e[8];
-#pragma unroll
-        for (uint32_t t = 0; t < 8u; ++t) {
-            const uint32_t k = 8u * g + t;
-            e[t] = k < a.din ? a.W1[(size_t)k * H + n] : (uint16_t)0;
-        }
+    if (tile) {
         v4f acc = {0.f, 0.f, 0.f, 0.f};
-        acc = mfma32(ld8(xs + r * 32u + 8u * g), pack8(e), acc);
+        acc = mfma32(ld8(xs + r * 32u + 8u * g), pack8(e1), acc);
         uint16_t hb[4];
 #pragma unroll
         for (uint32_t t = 0; t < 4u; ++t) {
             const uint32_t rr = 4u * g + t;
-            const float z = acc[t] + a.p[a.l.b1 + n];
+            const float z = acc[t] + b1n;
             z1s[rr * H + n] = z;
             hb[t] = f2bf(silu(z));
             h1s[rr * ldh + n] = hb[t];
@@ -472,61 +505,37 @@ __global__ void __launch_bounds__(kRowWaves * 64) mlp_train_rows(const TrainArgs
         st4(a.h1T + (size_t)n * a.Bp + row0 + 4u * g, hb[0], hb[1], hb[2], hb[3]);
     }
     __syncthreads();
-    // layer 2: z2 = h1 W2 + b2, B fragments from the transposed copy W2T[n][k]
-    for (uint32_t j = wave; j < ct; j += kRowWaves) {
-        const uint32_t n = 16u * j + r;
+    // layer 2: z2 = h1 W2 + b2, B fragments from the transposed copy W2T[n][k]; then the W2
+    // fragments of the dz1 step, in flight through layer 3 and the dz2 step
+    v8bf w2[kLoadAhead];
+    if (tile) {
         v4f acc = {0.f, 0.f, 0.f, 0.f};
-        for (uint32_t k0 = 0; k0 < H; k0 += 32u * kLoadAhead) {
-            v8bf wf[kLoadAhead];  // the chunk's weight fragments, in flight together
 #pragma unroll
-            for (uint32_t u = 0; u < kLoadAhead; ++u) {
-                const uint32_t k = k0 + 32u * u;
-                if (k < H) wf[u] = ld8(a.W2T + (size_t)n * H + k + 8u * g);
-            }
-#pragma unroll
-            for (uint32_t u = 0; u < kLoadAhead; ++u) {
-                const uint32_t k = k0 + 32u * u;
-                if (k < H) acc = mfma32(ld8(h1s + r * ldh + k + 8u * g), wf[u], acc);
-            }
-        }
+        for (uint32_t u = 0; u < kLoadAhead; ++u)
+            if (32u * u < H) acc = mfma32(ld8(h1s + r * ldh + 32u * u + 8u * g), w2t[u], acc);
         uint16_t hb[4];
 #pragma unroll
         for (uint32_t t = 0; t < 4u; ++t) {
             const uint32_t rr = 4u * g + t;
-            const float z = acc[t] + a.p[a.l.b2 + n];
+            const float z = acc[t] + b2n;
             z2s[rr * H + n] = z;
             hb[t] = f2bf(silu(z));
             h2s[rr * ldh + n] = hb[t];
         }
         st4(a.h2T + (size_t)n * a.Bp + row0 + 4u * g, hb[0], hb[1], hb[2], hb[3]);
+#pragma unroll
+        for (uint32_t u = 0; u < kLoadAhead; ++u)
+            if (32u * u < H) w2[u] = ld8(a.W2 + (size_t)n * H + 32u * u + 8u * g);
     }
     __syncthreads();
     // layer 3, loss and its gradient (one wave): y = h2 W3 + b3; dy = dloss/dy, zero past the batch
     if (wave == 0) {
         v4f acc = {0.f, 0.f, 0.f, 0.f};
-        // W3 column r (a lane past d_out reads column 0 and zeroes it: no branch around the
-        // loads, so a chunk's gathers are in flight together)
-        const bool rin = r < a.dout;
-        const uint32_t rc = rin ? r : 0u;
-        for (uint32_t k0 = 0; k0 < H; k0 += 32u * kGatherAhead) {
-            uint16_t e[kGatherAhead][8];
+        for (uint32_t k0 = 0; k0 < H; k0 += 32u) {
+            uint16_t e[8];  // W3 column r from LDS, zero past d_out
 #pragma unroll
-            for (uint32_t u = 0; u < kGatherAhead; ++u) {
-                const uint32_t k = k0 + 32u * u;
-                if (k < H) {
-#pragma unroll
-                    for (uint32_t t = 0; t < 8u; ++t) e[u][t] = a.W3[(size_t)(k + 8u * g + t) * a.dout + rc];
-                }
-            }
-#pragma unroll
-            for (uint32_t u = 0; u < kGatherAhead; ++u) {
-                const uint32_t k = k0 + 32u * u;
-                if (k < H) {
-#pragma unroll
-                    for (uint32_t t = 0; t < 8u; ++t) e[u][t] = rin ? e[u][t] : (uint16_t)0;
-                    acc = mfma32(ld8(h2s + r * ldh + k + 8u * g), pack8(e[u]), acc);
-                }
-            }
+            for (uint32_t t = 0; t < 8u; ++t) e[t] = r < a.dout ? w3s[(k0 + 8u * g + t) * a.dout + r] : (uint16_t)0;
+            acc = mfma32(ld8(h2s + r * ldh + k0 + 8u * g), pack8(e), acc);
         }
         float ls = 0.f;
         uint16_t db[4];
@@ -535,8 +544,7 @@ __global__ void __launch_bounds__(kRowWaves * 64) mlp_train_rows(const TrainArgs
             const uint32_t rr = 4u * g + t, row = row0 + rr;
             float dy = 0.f;
             if (row < a.B && r < a.dout) {
-                const uint32_t src = a.idx ? a.idx[row] : row;
-                const float d = acc[t] + a.p[a.l.b3 + r] - a.t[(size_t)src * a.dout + r];
+                const float d = acc[t] + b3r - tv[t];
                 if (a.kind == CAE_LOSS_MSE) {
                     dy = 2.0f * d * a.inv_n;
                     ls += d * d;
@@ -557,16 +565,15 @@ __global__ void __launch_bounds__(kRowWaves * 64) mlp_train_rows(const TrainArgs
     }
     __syncthreads();
     // dz2 = (dy W3^T) silu'(z2)  (one reduction step: d_out <= 16)
-    for (uint32_t j = wave; j < ct; j += kRowWaves) {
-        const uint32_t n = 16u * j + r;
-        uint16_t e[8];
+    if (tile) {
+        uint16_t e3[8];  // W3 row n from LDS, zero past d_out
 #pragma unroll
         for (uint32_t t = 0; t < 8u; ++t) {
             const uint32_t k = 8u * g + t;
-            e[t] = k < a.dout ? a.W3[(size_t)n * a.dout + k] : (uint16_t)0;
+            e3[t] = k < a.dout ? w3s[n * a.dout + k] : (uint16_t)0;
         }
         v4f acc = {0.f, 0.f, 0.f, 0.f};
-        acc = mfma32(ld8(dys + r * 32u + 8u * g), pack8(e), acc);
+        acc = mfma32(ld8(dys + r * 32u + 8u * g), pack8(e3), acc);
         uint16_t zb[4];
 #pragma unroll
         for (uint32_t t = 0; t < 4u; ++t) {
@@ -578,22 +585,11 @@ __global__ void __launch_bounds__(kRowWaves * 64) mlp_train_rows(const TrainArgs
     }
     __syncthreads();
     // dz1 = (dz2 W2^T) silu'(z1): B fragments W2[n][k], eight consecutive k
-    for (uint32_t j = wave; j < ct; j += kRowWaves) {
-        const uint32_t n = 16u * j + r;
+    if (tile) {
         v4f acc = {0.f, 0.f, 0.f, 0.f};
-        for (uint32_t k0 = 0; k0 < H; k0 += 32u * kLoadAhead) {
-            v8bf wf[kLoadAhead];
 #pragma unroll
-            for (uint32_t u = 0; u < kLoadAhead; ++u) {
-                const uint32_t k = k0 + 32u * u;
-                if (k < H) wf[u] = ld8(a.W2 + (size_t)n * H + k + 8u * g);
-            }
-#pragma unroll
-            for (uint32_t u = 0; u < kLoadAhead; ++u) {
-                const uint32_t k = k0 + 32u * u;
-                if (k < H) acc = mfma32(ld8(dzs + r * ldh + k + 8u * g), wf[u], acc);
-            }
-        }
+        for (uint32_t u = 0; u < kLoadAhead; ++u)
+            if (32u * u < H) acc = mfma32(ld8(dzs + r * ldh + 32u * u + 8u * g), w2[u], acc);
         uint16_t zb[4];
 #pragma unroll
         for (uint32_t t = 0; t < 4u; ++t) zb[t] = f2bf(acc[t] * dsilu(z1s[(4u * g + t) * H + n]));
@@ -920,7 +916,8 @@ int train_step_impl(const cae_mlp *net, const float *x, const float *target, con
     a.tiles1 = (din + 1u + 15u) / 16u * ct;
     a.tiles2 = (H / 16u + 1u) * ct;
     a.tiles3 = H / 16u + 1u;
-    const size_t lds = 2ull * (2u * kTrainRows * 32u + 3ull * kTrainRows * (H + kTrainPad)) + 8ull * kTrainRows * H;
+    const size_t lds = 2ull * (2u * kTrainRows * 32u + 3ull * kTrainRows * (H + kTrainPad)) + 8ull * kTrainRows * H +
+                       2ull * H * dout;  // + W3 in bf16
     hipLaunchKernelGGL(mlp_train_rows, dim3(a.Bp / kTrainRows), dim3(kRowWaves * 64u), lds, s, a);
     const uint32_t tiles = a.tiles1 + a.tiles2 + a.tiles3;
     hipLaunchKernelGGL(mlp_train_params, dim3(tiles), dim3(kParamSplit * 64u), 0, s, a);
