@@ -1885,18 +1885,34 @@ __device__ __forceinline__ void run_packed_seg(const EngineArgs &args, const Ite
                 atomicAdd(&bk[pad_word(w)], order_qty(o, pw2));
             }
             // further rows of SEG agents until every segment's market is done (the markets of a
-            // wave may have different populations)
+            // wave may have different populations), two rows at a time where both have agents:
+            // their generator chains are independent, and unmasked they share one basic block
             if (ballot(kSeg < A)) {
                 const PhiloxStep gen(s, d.id, args.k0, args.k1);
-                for (uint32_t b0 = kSeg;; b0 += kSeg) {
-                    const uint32_t a = b0 + ll;
-                    const bool on = a < A;
+                for (uint32_t b0 = kSeg;; b0 += 2u * kSeg) {
+                    const uint32_t a = b0 + ll, a2 = a + kSeg;
+                    const bool on = a < A, on2 = a2 < A;
                     if (!ballot(on)) break;
-                    if (on) {
-                        uint32_t w0, w1, w2, w3 = 0;
+                    if (ballot(on2)) {
+                        uint32_t w0, w1, w2, w3, v0, v1, v2, v3;
                         gen.words4(a, w0, w1, w2, w3);
-                        const uint32_t w = a >= o.n_noise ? other_word<false>(o, a, w0, w3) : noise_word(o, w0, w1);
-                        atomicAdd(&bk[pad_word(w)], order_qty(o, w2));
+                        gen.words4(a2, v0, v1, v2, v3);
+                        if (on) {
+                            const uint32_t w = a >= o.n_noise ? other_word<false>(o, a, w0, w3) : noise_word(o, w0, w1);
+                            atomicAdd(&bk[pad_word(w)], order_qty(o, w2));
+                        }
+                        if (on2) {
+                            const uint32_t w = a2 >= o.n_noise ? other_word<false>(o, a2, v0, v3) : noise_word(o, v0, v1);
+                            atomicAdd(&bk[pad_word(w)], order_qty(o, v2));
+                        }
+                    } else {
+                        if (on) {
+                            uint32_t w0, w1, w2, w3 = 0;
+                            gen.words4(a, w0, w1, w2, w3);
+                            const uint32_t w = a >= o.n_noise ? other_word<false>(o, a, w0, w3) : noise_word(o, w0, w1);
+                            atomicAdd(&bk[pad_word(w)], order_qty(o, w2));
+                        }
+                        break;
                     }
                 }
             }
